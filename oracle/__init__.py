@@ -46,6 +46,7 @@ def _load():
         "oracle_index_histogram": (None, [i64, u64p]),
         "oracle_metropolis": (ctypes.c_int, [f32p, i32p, i64, u32, u64, u32, i32p]),
         "oracle_metropolis_many": (ctypes.c_int, [f32p, i32p, i64, u32, u64, u32, i64]),
+        "oracle_metropolis_subset": (ctypes.c_int, [f32p, i64, u32, u64, u32, P(i64), i64, i32p]),
         "oracle_cumulative": (ctypes.c_int, [f32p, i64, f64p, f32p, i32p]),
         "oracle_cumulative_extended": (ctypes.c_int, [f32p, i64, f64p, f64p]),
         "oracle_search": (i64, [f64p, i64, ctypes.c_double]),
@@ -150,6 +151,17 @@ def metropolis_many(lw, B, seed, inst0, n_inst):
                                        lw.size, int(B), int(seed), int(inst0), int(n_inst)),
            "metropolis_many")
     return anc
+
+
+def metropolis_subset(lw, B, seed, instance, idx):
+    """Metropolis ancestors of the particles in idx only."""
+    lw = _f32(lw)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    out = np.empty(idx.size, dtype=np.int32)
+    _check(_lib.oracle_metropolis_subset(_ptr(lw, ctypes.c_float), lw.size, int(B), int(seed),
+                                         int(instance), _ptr(idx, ctypes.c_int64), idx.size,
+                                         _ptr(out, ctypes.c_int32)), "metropolis_subset")
+    return out
 
 
 def cumulative(lw):

@@ -185,6 +185,19 @@ int oracle_metropolis(const float *lw, int32_t *anc, int64_t P, uint32_t B, uint
     return 0;
 }
 
+/* The chains of the particles listed in idx[0..n) only (same results as   */
+/* the full resampling at those positions).                                */
+int oracle_metropolis_subset(const float *lw, int64_t P, uint32_t B, uint64_t seed,
+                             uint32_t instance, const int64_t *idx, int64_t n, int32_t *out)
+{
+    if (!lw || !idx || !out || P < 1 || P > INT32_MAX || n < 0) return ORACLE_EINVAL;
+    for (int64_t s = 0; s < n; ++s) {
+        if (idx[s] < 0 || idx[s] >= P) return ORACLE_EINVAL;
+        out[s] = metropolis_chain(lw, P, B, seed, instance, idx[s]);
+    }
+    return 0;
+}
+
 /* Many independent resamplings of one weight vector, instances inst0 ..   */
 /* inst0 + n_inst - 1, written row by row into anc[n_inst * P].            */
 int oracle_metropolis_many(const float *lw, int32_t *anc, int64_t P, uint32_t B, uint64_t seed,

@@ -1,0 +1,194 @@
+"""Python binding of the resampling library: same names as the C ABI in
+include/resample.h, torch tensors in place of device pointers.
+
+This layer only marshals arguments: it checks dtype, device and contiguity,
+allocates outputs the caller did not pass, keeps a zero-initialised pooled
+workspace per (device, stream), and passes data pointers and the current HIP
+stream to libresample.so. Every step of the computation runs in the library's
+kernels.
+"""
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import check, lib
+
+STRATIFIED, SYSTEMATIC, MULTINOMIAL, METROPOLIS, LOG_SUM_EXP = (
+    _lib.STRATIFIED, _lib.SYSTEMATIC, _lib.MULTINOMIAL, _lib.METROPOLIS, _lib.LOG_SUM_EXP)
+FLAG_NAN, FLAG_POSINF, FLAG_ALL_NEGINF, FLAG_BAD_ANCESTOR, FLAG_INTERNAL = (
+    _lib.FLAG_NAN, _lib.FLAG_POSINF, _lib.FLAG_ALL_NEGINF, _lib.FLAG_BAD_ANCESTOR,
+    _lib.FLAG_INTERNAL)
+
+
+def _stream_handle(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _need(t, dtype, name, numel=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must live on the GPU")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    return t
+
+
+_workspaces = {}
+
+
+def workspace_bytes(P, kind):
+    return int(lib.rs_workspace_bytes(int(P), int(kind)))
+
+
+def workspace(P, kind, device=None, stream=None):
+    """Pooled, zero-initialised workspace for `kind` at size P on (device, stream).
+
+    The library leaves a workspace reusable after every call, so one buffer
+    serves all calls ordered on the same stream.
+    """
+    device = torch.device(device) if device is not None else torch.device(
+        "cuda", torch.cuda.current_device())
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    need = workspace_bytes(P, kind)
+    key = (device.index, s.cuda_stream)
+    buf = _workspaces.get(key)
+    if buf is None or buf.numel() < need:
+        with torch.cuda.stream(s):
+            buf = torch.zeros(max(need, 256), dtype=torch.uint8, device=device)
+        _workspaces[key] = buf
+    return buf
+
+
+def _status_ptr(status):
+    if status is None:
+        return None
+    _need(status, torch.int32, "status")
+    return _ptr(status)
+
+
+def resample_metropolis(lw, B, seed, instance=0, anc=None, status=None, stream=None):
+    _need(lw, torch.float32, "lw")
+    P = lw.numel()
+    anc = torch.empty(P, dtype=torch.int32, device=lw.device) if anc is None else anc
+    _need(anc, torch.int32, "anc", P)
+    check(lib.resample_metropolis(_ptr(lw), _ptr(anc), P, int(B), int(seed), int(instance),
+                                  _status_ptr(status), _stream_handle(stream)),
+          "resample_metropolis")
+    return anc
+
+
+def _prefix(fn, kind, lw, seed, instance, anc, cumw, ws, status, stream):
+    _need(lw, torch.float32, "lw")
+    P = lw.numel()
+    anc = torch.empty(P, dtype=torch.int32, device=lw.device) if anc is None else anc
+    _need(anc, torch.int32, "anc", P)
+    if cumw is not None:
+        _need(cumw, torch.float64, "cumw", P)
+    if ws is None:
+        ws = workspace(P, kind, lw.device, stream)
+    _need(ws, torch.uint8, "ws")
+    check(fn(_ptr(lw), _ptr(anc), P, int(seed), int(instance), _ptr(cumw), _ptr(ws), ws.numel(),
+             _status_ptr(status), _stream_handle(stream)), fn.__name__)
+    return anc
+
+
+def resample_stratified(lw, seed, instance=0, anc=None, cumw=None, ws=None, status=None,
+                        stream=None):
+    return _prefix(lib.resample_stratified, STRATIFIED, lw, seed, instance, anc, cumw, ws, status,
+                   stream)
+
+
+def resample_systematic(lw, seed, instance=0, anc=None, cumw=None, ws=None, status=None,
+                        stream=None):
+    return _prefix(lib.resample_systematic, SYSTEMATIC, lw, seed, instance, anc, cumw, ws, status,
+                   stream)
+
+
+def resample_multinomial(lw, seed, instance=0, anc=None, cumw=None, ws=None, status=None,
+                         stream=None):
+    return _prefix(lib.resample_multinomial, MULTINOMIAL, lw, seed, instance, anc, cumw, ws,
+                   status, stream)
+
+
+def ancestors_to_offspring(anc, off=None, status=None, stream=None):
+    _need(anc, torch.int32, "anc")
+    P = anc.numel()
+    off = torch.empty(P, dtype=torch.int32, device=anc.device) if off is None else off
+    _need(off, torch.int32, "off", P)
+    check(lib.ancestors_to_offspring(_ptr(anc), _ptr(off), P, _status_ptr(status),
+                                     _stream_handle(stream)), "ancestors_to_offspring")
+    return off
+
+
+def permute_copy(anc, x_in, x_out=None, status=None, stream=None):
+    _need(anc, torch.int32, "anc")
+    _need(x_in, torch.float32, "x_in")
+    P = anc.numel()
+    if P == 0:
+        return torch.empty_like(x_in) if x_out is None else x_out
+    if x_in.numel() % P:
+        raise ValueError("x_in must hold P rows")
+    D = x_in.numel() // P
+    x_out = torch.empty_like(x_in) if x_out is None else x_out
+    _need(x_out, torch.float32, "x_out", x_in.numel())
+    check(lib.permute_copy(_ptr(anc), _ptr(x_in), _ptr(x_out), P, D, _status_ptr(status),
+                           _stream_handle(stream)), "permute_copy")
+    return x_out
+
+
+def rs_log_sum_exp(lw, out=None, ws=None, status=None, stream=None):
+    _need(lw, torch.float32, "lw")
+    P = lw.numel()
+    out = torch.empty(1, dtype=torch.float64, device=lw.device) if out is None else out
+    _need(out, torch.float64, "out")
+    if ws is None:
+        ws = workspace(P, LOG_SUM_EXP, lw.device, stream)
+    check(lib.rs_log_sum_exp(_ptr(lw), P, _ptr(out), _ptr(ws), ws.numel(), _status_ptr(status),
+                             _stream_handle(stream)), "rs_log_sum_exp")
+    return out
+
+
+def rs_log_u_table(approx=None, exact=None, stream=None):
+    """Both logs of the 2^23-point u grid (see include/resample.h)."""
+    dev = torch.device("cuda", torch.cuda.current_device())
+    approx = torch.empty(1 << 23, dtype=torch.float32, device=dev) if approx is None else approx
+    exact = torch.empty(1 << 23, dtype=torch.float32, device=dev) if exact is None else exact
+    _need(approx, torch.float32, "approx", 1 << 23)
+    _need(exact, torch.float32, "exact", 1 << 23)
+    check(lib.rs_log_u_table(_ptr(approx), _ptr(exact), _stream_handle(stream)), "rs_log_u_table")
+    return approx, exact
+
+
+def metropolis_B(P, w_max, eps):
+    return int(lib.metropolis_B(int(P), float(w_max), float(eps)))
+
+
+def rs_metropolis_set_tuning(block, unroll, lds_max_p, lanes_per_chain=0):
+    t = _lib.Tuning(int(block), int(unroll), int(lds_max_p), int(lanes_per_chain))
+    check(lib.rs_metropolis_set_tuning(ctypes.byref(t)), "rs_metropolis_set_tuning")
+
+
+def rs_metropolis_get_tuning():
+    t = _lib.Tuning()
+    check(lib.rs_metropolis_get_tuning(ctypes.byref(t)), "rs_metropolis_get_tuning")
+    return dict(block=t.block, unroll=t.unroll, lds_max_p=t.lds_max_p,
+                lanes_per_chain=t.lanes_per_chain)
+
+
+RESAMPLERS = {
+    "metropolis": resample_metropolis,
+    "stratified": resample_stratified,
+    "systematic": resample_systematic,
+    "multinomial": resample_multinomial,
+}

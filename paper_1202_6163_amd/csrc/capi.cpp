@@ -1,0 +1,224 @@
+// C ABI of the resampling library: argument checking, workspace sizing,
+// Metropolis launch tuning and the host-side iteration-count helper. Every
+// check here happens before any kernel is enqueued.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <mutex>
+
+#include "launch.h"
+#include "prefix.h"
+#include "resample.h"
+
+namespace {
+
+constexpr int64_t kMaxP = 2147483647;  // ancestors are int32
+
+std::mutex g_tune_mutex;
+bool g_tune_init = false;
+rs::MetropolisTuning g_tune{256, 8, 16384, 0};
+
+bool valid_tuning(const rs::MetropolisTuning &t)
+{
+    const bool lpc_ok = t.lanes_per_chain == 0 ||
+                        (t.lanes_per_chain >= 1 && t.lanes_per_chain <= 64 &&
+                         (t.lanes_per_chain & (t.lanes_per_chain - 1)) == 0);
+    const bool unroll_ok = t.unroll == 2 || t.unroll == 4 || t.unroll == 8 || t.unroll == 16;
+    return t.block >= 64 && t.block <= 1024 && t.block % 64 == 0 && unroll_ok &&
+           t.lds_max_p >= 0 && lpc_ok;
+}
+
+long env_long(const char *name, long fallback)
+{
+    const char *s = std::getenv(name);
+    if (!s || !*s) return fallback;
+    char *end = nullptr;
+    const long v = std::strtol(s, &end, 10);
+    return (end && *end == '\0') ? v : fallback;
+}
+
+// Environment overrides pick launch parameters only, never another code path.
+rs::MetropolisTuning current_tuning()
+{
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    if (!g_tune_init) {
+        rs::MetropolisTuning t = g_tune;
+        t.block = (int32_t)env_long("RS_BLOCK", t.block);
+        t.unroll = (int32_t)env_long("RS_UNROLL", t.unroll);
+        t.lds_max_p = (int64_t)env_long("RS_LDS_MAX_P", (long)t.lds_max_p);
+        t.lanes_per_chain = (int32_t)env_long("RS_LANES_PER_CHAIN", t.lanes_per_chain);
+        if (valid_tuning(t)) g_tune = t;
+        g_tune_init = true;
+    }
+    return g_tune;
+}
+
+bool overlaps(const void *a, size_t abytes, const void *b, size_t bbytes)
+{
+    const uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+    return a0 < b0 + bbytes && b0 < a0 + abytes;
+}
+
+int map_rc(int rc) { return rc == 0 ? RS_OK : (rc == -1 ? RS_EINVAL : RS_EHIP); }
+
+int prefix_call(int kind, const float *lw, int32_t *anc, int64_t P, uint64_t seed,
+                uint32_t instance, double *cumw, void *ws, size_t ws_bytes, int32_t *status,
+                hipStream_t stream)
+{
+    if (P == 0) return RS_OK;
+    if (!lw || !anc || !ws || P < 0 || P > kMaxP) return RS_EINVAL;
+    const size_t p = (size_t)P;
+    if (overlaps(lw, 4 * p, anc, 4 * p)) return RS_EINVAL;
+    if (cumw && (overlaps(cumw, 8 * p, lw, 4 * p) || overlaps(cumw, 8 * p, anc, 4 * p)))
+        return RS_EINVAL;
+    if (ws_bytes < rs_workspace_bytes(P, kind)) return RS_EWORKSPACE;
+    if (overlaps(ws, ws_bytes, lw, 4 * p) || overlaps(ws, ws_bytes, anc, 4 * p)) return RS_EINVAL;
+    return map_rc(rs::launch_prefix(kind, lw, anc, P, seed, instance, cumw, ws, status, stream));
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *rs_strerror(int code)
+{
+    switch (code) {
+    case RS_OK: return "success";
+    case RS_EINVAL: return "invalid argument";
+    case RS_EWORKSPACE: return "workspace too small";
+    case RS_EHIP: return "HIP launch failure";
+    default: return "unknown error";
+    }
+}
+
+int rs_version(void) { return 100; }
+
+size_t rs_workspace_bytes(int64_t P, int resampler)
+{
+    if (P < 1) return 0;
+    switch (resampler) {
+    case RS_STRATIFIED:
+    case RS_SYSTEMATIC:
+    case RS_LOG_SUM_EXP: return rs::ws_layout(P, false).total;
+    case RS_MULTINOMIAL: return rs::ws_layout(P, true).total;
+    default: return 0;
+    }
+}
+
+int rs_workspace_init(void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (ws_bytes == 0) return RS_OK;
+    if (!ws) return RS_EINVAL;
+    return map_rc(rs::launch_zero(ws, ws_bytes, stream));
+}
+
+int resample_metropolis(const float *lw, int32_t *anc, int64_t P, uint32_t B, uint64_t seed,
+                        uint32_t instance, int32_t *status, hipStream_t stream)
+{
+    if (P == 0) return RS_OK;
+    if (!lw || !anc || P < 0 || P > kMaxP) return RS_EINVAL;
+    if (overlaps(lw, 4 * (size_t)P, anc, 4 * (size_t)P)) return RS_EINVAL;
+    const rs::MetropolisTuning t = current_tuning();
+    return map_rc(rs::launch_metropolis(lw, anc, P, B, seed, instance, status, t, stream));
+}
+
+int resample_stratified(const float *lw, int32_t *anc, int64_t P, uint64_t seed, uint32_t instance,
+                        double *cumw, void *ws, size_t ws_bytes, int32_t *status,
+                        hipStream_t stream)
+{
+    return prefix_call(RS_STRATIFIED, lw, anc, P, seed, instance, cumw, ws, ws_bytes, status,
+                       stream);
+}
+
+int resample_systematic(const float *lw, int32_t *anc, int64_t P, uint64_t seed, uint32_t instance,
+                        double *cumw, void *ws, size_t ws_bytes, int32_t *status,
+                        hipStream_t stream)
+{
+    return prefix_call(RS_SYSTEMATIC, lw, anc, P, seed, instance, cumw, ws, ws_bytes, status,
+                       stream);
+}
+
+int resample_multinomial(const float *lw, int32_t *anc, int64_t P, uint64_t seed,
+                         uint32_t instance, double *cumw, void *ws, size_t ws_bytes,
+                         int32_t *status, hipStream_t stream)
+{
+    return prefix_call(RS_MULTINOMIAL, lw, anc, P, seed, instance, cumw, ws, ws_bytes, status,
+                       stream);
+}
+
+int ancestors_to_offspring(const int32_t *anc, int32_t *off, int64_t P, int32_t *status,
+                           hipStream_t stream)
+{
+    if (P == 0) return RS_OK;
+    if (!anc || !off || P < 0 || P > kMaxP) return RS_EINVAL;
+    if (overlaps(anc, 4 * (size_t)P, off, 4 * (size_t)P)) return RS_EINVAL;
+    return map_rc(rs::launch_offspring(anc, off, P, status, stream));
+}
+
+int permute_copy(const int32_t *anc, const float *x_in, float *x_out, int64_t P, int32_t D,
+                 int32_t *status, hipStream_t stream)
+{
+    if (P == 0) return RS_OK;
+    if (!anc || !x_in || !x_out || P < 0 || P > kMaxP || D < 1) return RS_EINVAL;
+    const size_t rows = (size_t)P * (size_t)D * sizeof(float);
+    if (overlaps(x_in, rows, x_out, rows) || overlaps(anc, 4 * (size_t)P, x_out, rows))
+        return RS_EINVAL;
+    return map_rc(rs::launch_permute_copy(anc, x_in, x_out, P, D, status, stream));
+}
+
+int rs_log_sum_exp(const float *lw, int64_t P, double *out, void *ws, size_t ws_bytes,
+                   int32_t *status, hipStream_t stream)
+{
+    if (!lw || !out || !ws || P < 1 || P > kMaxP) return RS_EINVAL;
+    if (ws_bytes < rs_workspace_bytes(P, RS_LOG_SUM_EXP)) return RS_EWORKSPACE;
+    return map_rc(rs::launch_log_sum_exp(lw, P, out, ws, status, stream));
+}
+
+uint32_t metropolis_B(int64_t P, double w_max, double eps)
+{
+    // Eq. (4): lambda^B <= eps (alpha + beta) / max(alpha, beta); eq. (5)
+    // solves it for 0 < lambda < 1. lambda = 0 (uniform weights) needs one step.
+    if (P < 2 || !(w_max > 0.0) || w_max > 1.0 || !(eps > 0.0)) return 0;
+    const double beta = 1.0 / (double)P;
+    const double alpha = (1.0 - w_max) / ((double)P * w_max);
+    const double lambda = 1.0 - alpha - beta;
+    const double rhs = eps * (alpha + beta) / std::fmax(alpha, beta);
+    if (rhs >= 1.0) return 0;
+    if (!(lambda > 0.0)) return 1;
+    const double b = std::ceil(std::log(rhs) / std::log(lambda));
+    if (!(b > 0.0)) return 0;
+    if (b >= 4294967295.0) return 4294967295u;
+    return (uint32_t)b;
+}
+
+int rs_log_u_table(float *approx, float *exact, hipStream_t stream)
+{
+    if (!approx && !exact) return RS_EINVAL;
+    if (approx && exact && overlaps(approx, 4u << 23, exact, 4u << 23)) return RS_EINVAL;
+    return map_rc(rs::launch_log_u_table(approx, exact, stream));
+}
+
+int rs_metropolis_set_tuning(const rs_metropolis_tuning *t)
+{
+    if (!t) return RS_EINVAL;
+    const rs::MetropolisTuning v{t->block, t->unroll, t->lds_max_p, t->lanes_per_chain};
+    if (!valid_tuning(v)) return RS_EINVAL;
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    g_tune = v;
+    g_tune_init = true;
+    return RS_OK;
+}
+
+int rs_metropolis_get_tuning(rs_metropolis_tuning *t)
+{
+    if (!t) return RS_EINVAL;
+    const rs::MetropolisTuning v = current_tuning();
+    t->block = v.block;
+    t->unroll = v.unroll;
+    t->lds_max_p = v.lds_max_p;
+    t->lanes_per_chain = v.lanes_per_chain;
+    return RS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,145 @@
+// Device building blocks shared by the resampling kernels (gfx950, wave64).
+//
+// Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random
+// numbers: as easy as 1, 2, 3", SC'11), counter-based, so any draw is
+// addressed by (seed, counter) with no per-thread state. Counter words are
+// (c0, c1, c2, c3) = (particle or particle group, instance, draw block, tag).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rs {
+
+constexpr int kWave = 64;
+
+// Counter tags: which step of the method a Philox block feeds.
+constexpr uint32_t kTagMetropolis = 1u;
+constexpr uint32_t kTagStratified = 2u;
+constexpr uint32_t kTagSystematic = 3u;
+constexpr uint32_t kTagMultinomial = 4u;
+constexpr uint32_t kTagFilterNoise = 5u;
+
+// Status bits (mirror RS_FLAG_* in resample.h).
+constexpr int kFlagNan = 1;
+constexpr int kFlagPosInf = 2;
+constexpr int kFlagAllNegInf = 4;
+constexpr int kFlagBadAncestor = 8;
+constexpr int kFlagInternal = 16;
+
+struct Block4 {
+    uint32_t r0, r1, r2, r3;
+};
+
+// Ten Philox rounds: two 32x32->64 products per round (multipliers from the
+// SC'11 paper); the key advances by the Weyl increments between rounds.
+__device__ __forceinline__ Block4 philox(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2,
+                                         uint32_t c3)
+{
+    uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return Block4{c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ uint32_t word(const Block4 &b, uint32_t k)
+{
+    return k == 0 ? b.r0 : k == 1 ? b.r1 : k == 2 ? b.r2 : b.r3;
+}
+
+// Uniform index in [0, P): the high word of r * P.
+__device__ __forceinline__ uint32_t uniform_index(uint32_t r, uint32_t P)
+{
+    return (uint32_t)(((uint64_t)r * (uint64_t)P) >> 32);
+}
+
+// Uniform on the open binary32 grid (2m + 1) 2^-24, m = r >> 9.
+__device__ __forceinline__ float grid_uniform(uint32_t r)
+{
+    return (float)(2u * (r >> 9) + 1u) * 0x1p-24f;
+}
+
+// Correctly rounded binary32 log of a grid uniform, via the binary64 log.
+__device__ __forceinline__ float exact_log_u(float u)
+{
+    return (float)log((double)u);
+}
+
+// Uniform in [0, 1) with 32 random bits, as binary64.
+__device__ __forceinline__ double unit32(uint32_t r)
+{
+    return (double)r * 0x1p-32;
+}
+
+// Uniform in [0, 1) with 53 random bits, as binary64.
+__device__ __forceinline__ double unit53(uint32_t a, uint32_t b)
+{
+    return (double)(((uint64_t)a << 21) | (uint64_t)(b >> 11)) * 0x1p-53;
+}
+
+// ---------------------------------------------------------------- wave ops
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
+__device__ __forceinline__ int wave_id() { return (int)(threadIdx.x / kWave); }
+
+__device__ __forceinline__ double wave_inclusive_sum(double v)
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        double y = __shfl_up(v, off, kWave);
+        if (lane >= off) v += y;
+    }
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+__device__ __forceinline__ float wave_max(float v)
+{
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+
+__device__ __forceinline__ int wave_or(int v)
+{
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v |= __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// Largest binary64 strictly below a positive finite b.
+__device__ __forceinline__ double below(double b)
+{
+    return __longlong_as_double(__double_as_longlong(b) - 1);
+}
+
+__device__ __forceinline__ void raise_flags(int32_t *status, int flags)
+{
+    if (flags && status) atomicOr(status, flags);
+}
+
+}  // namespace rs

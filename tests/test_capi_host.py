@@ -1,0 +1,111 @@
+"""The C ABI on the host (CPU only): the library loads, exports every function
+include/resample.h declares, and rejects bad arguments before any launch.
+No kernel is enqueued by these tests."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_1202_6163_amd", "libresample.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libresample.so not built")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1202_6163_amd import _lib
+    return _lib
+
+
+def test_exports_every_declared_function(L):
+    names = L.header_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(L.lib, name), name
+    # and the shared object's dynamic symbol table agrees
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (\w+)$", out, flags=re.M))
+    assert set(names) <= exported
+
+
+def test_strerror_and_version(L):
+    assert L.lib.rs_strerror(0) == b"success"
+    assert L.lib.rs_strerror(-1) == b"invalid argument"
+    assert L.lib.rs_strerror(-2) == b"workspace too small"
+    assert L.lib.rs_strerror(12345) == b"unknown error"
+    assert L.lib.rs_version() >= 100
+
+
+def test_argument_errors_before_launch(L):
+    lib = L.lib
+    fake = ctypes.c_void_p(0x10000000)
+    other = ctypes.c_void_p(0x20000000)
+    ws = ctypes.c_void_p(0x30000000)
+    # null pointers, negative sizes, P beyond int32 ancestors
+    assert lib.resample_metropolis(None, other, 10, 4, 1, 0, None, None) == L.RS_EINVAL
+    assert lib.resample_metropolis(fake, other, -1, 4, 1, 0, None, None) == L.RS_EINVAL
+    assert lib.resample_metropolis(fake, other, 2**31, 4, 1, 0, None, None) == L.RS_EINVAL
+    # overlapping input and output
+    assert lib.resample_metropolis(fake, ctypes.c_void_p(0x10000004), 10, 4, 1, 0, None,
+                                   None) == L.RS_EINVAL
+    for fn in (lib.resample_stratified, lib.resample_systematic, lib.resample_multinomial):
+        assert fn(None, other, 10, 1, 0, None, ws, 1 << 20, None, None) == L.RS_EINVAL
+        assert fn(fake, other, 10, 1, 0, None, None, 1 << 20, None, None) == L.RS_EINVAL
+        assert fn(fake, other, 10, 1, 0, None, ws, 1, None, None) == L.RS_EWORKSPACE
+        assert fn(fake, fake, 10, 1, 0, None, ws, 1 << 20, None, None) == L.RS_EINVAL
+    assert lib.permute_copy(fake, other, other, 10, 4, None, None) == L.RS_EINVAL
+    assert lib.permute_copy(fake, other, ws, 10, 0, None, None) == L.RS_EINVAL
+    assert lib.ancestors_to_offspring(fake, fake, 10, None, None) == L.RS_EINVAL
+    assert lib.rs_log_sum_exp(fake, 10, other, ws, 1, None, None) == L.RS_EWORKSPACE
+    assert lib.rs_log_u_table(None, None, None) == L.RS_EINVAL
+
+
+def test_empty_resampling_is_a_no_op(L):
+    lib = L.lib
+    assert lib.resample_metropolis(None, None, 0, 4, 1, 0, None, None) == L.RS_OK
+    assert lib.resample_stratified(None, None, 0, 1, 0, None, None, 0, None, None) == L.RS_OK
+    assert lib.permute_copy(None, None, None, 0, 4, None, None) == L.RS_OK
+    assert lib.ancestors_to_offspring(None, None, 0, None, None) == L.RS_OK
+
+
+def test_workspace_bytes(L):
+    lib = L.lib
+    assert lib.rs_workspace_bytes(0, 0) == 0
+    assert lib.rs_workspace_bytes(1 << 20, L.METROPOLIS) == 0
+    prev = 0
+    for P in (1, 1000, 1024, 1025, 1 << 20, (1 << 31) - 1):
+        b = lib.rs_workspace_bytes(P, L.STRATIFIED)
+        assert b >= prev and b % 256 == 0
+        prev = b
+        assert lib.rs_workspace_bytes(P, L.MULTINOMIAL) >= b + 8 * P
+        assert lib.rs_workspace_bytes(P, L.SYSTEMATIC) == b
+
+
+def test_tuning_validation(L):
+    t = L.Tuning()
+    assert L.lib.rs_metropolis_get_tuning(ctypes.byref(t)) == 0
+    saved = L.Tuning(t.block, t.unroll, t.lds_max_p, t.lanes_per_chain)
+    for bad in ((32, 8, 0, 0), (256, 3, 0, 0), (256, 8, -1, 0), (256, 8, 0, 3), (2048, 8, 0, 0)):
+        assert L.lib.rs_metropolis_set_tuning(ctypes.byref(L.Tuning(*bad))) == L.RS_EINVAL
+    assert L.lib.rs_metropolis_set_tuning(ctypes.byref(L.Tuning(512, 4, 1000, 8))) == 0
+    assert L.lib.rs_metropolis_get_tuning(ctypes.byref(t)) == 0
+    assert (t.block, t.unroll, t.lds_max_p, t.lanes_per_chain) == (512, 4, 1000, 8)
+    assert L.lib.rs_metropolis_set_tuning(ctypes.byref(saved)) == 0
+
+
+def test_metropolis_B_matches_oracle(L):
+    rng = np.random.default_rng(11)
+    for _ in range(2000):
+        P = int(rng.integers(1, 1 << 24))
+        w_max = float(np.exp(rng.uniform(np.log(1.0 / P), 0)))
+        eps = float(10 ** rng.uniform(-4, -0.5))
+        assert L.lib.metropolis_B(P, w_max, eps) == oracle.metropolis_B(P, w_max, eps)
+    assert L.lib.metropolis_B(4096, 1.0 / 4096, 1e-3) == 1
+    assert L.lib.metropolis_B(1, 1.0, 1e-3) == 0
+    assert L.lib.metropolis_B(100, 0.0, 1e-3) == 0

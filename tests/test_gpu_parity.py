@@ -1,0 +1,337 @@
+"""GPU parity: the HIP library through its C ABI against the CPU oracle.
+
+Bar (written here, per output):
+  - Metropolis ancestors, offspring counts and the state copy: bit-exact.
+  - Cumulative weights: within 1e-6 relative of the binary64 oracle.
+  - Stratified / systematic / multinomial ancestors: identical except draws
+    within 1e-6 relative of a cumulative-weight boundary (counted, printed).
+Sizes span several 1024-weight tiles with ragged tails, up to P = 2^20 (the
+largest workload) in the launch configuration the benchmark uses.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from parity import ORACLE_FN, check_cumw, explained_mismatches
+from paper_1202_6163_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rs():
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    import paper_1202_6163_amd.api as api
+    return api
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+# ----------------------------------------------------------------- Metropolis
+def test_log_u_fast_path_premise(rs):
+    approx, exact = rs.rs_log_u_table()
+    a, e = host(approx), host(exact)
+    ref = oracle.log_u_table()
+    assert np.array_equal(e.view(np.uint32), ref.view(np.uint32)), "device binary64 log differs"
+    rel = np.abs(a.astype(np.float64) - e.astype(np.float64)) / np.abs(a.astype(np.float64))
+    say("hardware log: max relative error on the u grid", rel.max())
+    assert rel.max() <= 2.0**-20
+
+
+METRO_CASES = [
+    (1024, 1.0, 32, 1, 0),      # the small single-resample case
+    (1, 1.0, 16, 3, 0),
+    (2, 0.5, 5, 3, 7),
+    (3, 2.0, 9, 4, 1),
+    (1000, 4.0, 64, 5, 2),
+    (4097, 0.25, 7, 6, 3),
+    (16384, 1.0, 64, 7, 4),
+    (65537, 2.0, 33, 8, 5),
+    (40000, 1.0, 17, 9, 6),
+]
+
+TUNINGS = [
+    (256, 8, 16384, 0),
+    (64, 2, 0, 1),
+    (1024, 16, 1 << 30, 1),
+    (256, 4, 1 << 30, 4),
+    (128, 8, 0, 64),
+    (512, 2, 1 << 30, 16),
+]
+
+
+@pytest.fixture
+def tuning(rs):
+    saved = rs.rs_metropolis_get_tuning()
+    yield
+    rs.rs_metropolis_set_tuning(**saved)
+
+
+@pytest.mark.parametrize("P,sigma,B,seed,inst", METRO_CASES)
+def test_metropolis_bit_exact(rs, tuning, P, sigma, B, seed, inst):
+    lw = workloads.normal_logweights(P, sigma, seed) if P != 1024 else workloads.small_case_logweights()
+    ref, st = oracle.metropolis(lw, B, seed, inst)
+    g = dev(lw)
+    for t in TUNINGS:
+        say("metropolis", P, sigma, B, "tuning", t)
+        rs.rs_metropolis_set_tuning(*t)
+        anc = host(rs.resample_metropolis(g, B, seed, inst))
+        assert np.array_equal(anc, ref), f"tuning {t}: {np.count_nonzero(anc != ref)} differ"
+
+
+def test_metropolis_B_zero_and_special_weights(rs):
+    P = 5000
+    lw = workloads.normal_logweights(P, 1.0, 3)
+    assert np.array_equal(host(rs.resample_metropolis(dev(lw), 0, 1)), np.arange(P))
+    lw2 = lw.copy()
+    lw2[::3] = -np.inf
+    lw2[7] = 3.0
+    ref, _ = oracle.metropolis(lw2, 40, 2, 9)
+    assert np.array_equal(host(rs.resample_metropolis(dev(lw2), 40, 2, 9)), ref)
+    eq = np.full(P, 0.5, dtype=np.float32)
+    ref, _ = oracle.metropolis(eq, 11, 4, 0)
+    assert np.array_equal(host(rs.resample_metropolis(dev(eq), 11, 4, 0)), ref)
+
+
+def test_metropolis_status_flags(rs):
+    lw = np.zeros(300, dtype=np.float32)
+    lw[10] = np.nan
+    lw[20] = np.inf
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    anc = host(rs.resample_metropolis(dev(lw), 8, 1, status=st))
+    assert int(host(st)[0]) == rs.FLAG_NAN | rs.FLAG_POSINF
+    ref, fl = oracle.metropolis(lw, 8, 1)
+    assert fl == rs.FLAG_NAN | rs.FLAG_POSINF
+    assert np.array_equal(anc, ref)  # defined outputs agree too
+
+
+@pytest.mark.parametrize("B", [32, 64, 512])
+@pytest.mark.parametrize("sigma", [0.25, 1.0, 4.0])
+def test_metropolis_full_size(rs, B, sigma):
+    P = 1 << 20
+    lw = workloads.normal_logweights(P, sigma, 0)
+    say("metropolis P=2^20", sigma, B)
+    anc = host(rs.resample_metropolis(dev(lw), B, 0, 0))
+    if B <= 64:
+        ref, _ = oracle.metropolis(lw, B, 0, 0)
+        assert np.array_equal(anc, ref)
+    else:
+        idx = np.random.default_rng(B).choice(P, 4096, replace=False)
+        idx[:2] = [0, P - 1]
+        ref = oracle.metropolis_subset(lw, B, 0, 0, idx)
+        assert np.array_equal(anc[idx], ref)
+
+
+def test_metropolis_deterministic(rs):
+    lw = dev(workloads.normal_logweights(1 << 18, 1.0, 5))
+    a = host(rs.resample_metropolis(lw, 64, 9, 1))
+    b = host(rs.resample_metropolis(lw, 64, 9, 1))
+    assert np.array_equal(a, b)
+
+
+# ----------------------------------------------------------------- prefix resamplers
+PREFIX = ["stratified", "systematic", "multinomial"]
+SIZES = [1, 2, 3, 1023, 1024, 1025, 4097, 100003, 1 << 16]
+
+
+@pytest.mark.parametrize("kind", PREFIX)
+@pytest.mark.parametrize("P", SIZES)
+@pytest.mark.parametrize("sigma", [0.5, 2.0])
+def test_prefix_parity(rs, kind, P, sigma):
+    seed, inst = P % 97 + 1, 3
+    lw = workloads.normal_logweights(P, sigma, seed)
+    anc_o, st_o, C_o = ORACLE_FN[kind](lw, seed, inst, want_cumw=True)
+    g = dev(lw)
+    C = torch.empty(P, dtype=torch.float64, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    anc = getattr(rs, f"resample_{kind}")(g, seed, inst, cumw=C, status=st)
+    anc_g, C_g = host(anc), host(C)
+    assert int(host(st)[0]) == 0
+    check_cumw(C_g, C_o)
+    n = explained_mismatches(kind, anc_g, anc_o, C_o, seed, inst)
+    if n:
+        say(f"{kind} P={P} sigma={sigma}: {n} boundary mismatches (explained)")
+    # the same call without cumw gives the same ancestors
+    anc2 = host(getattr(rs, f"resample_{kind}")(g, seed, inst))
+    assert np.array_equal(anc2, anc_g)
+
+
+@pytest.mark.parametrize("kind", PREFIX)
+@pytest.mark.parametrize("sigma", [0.25, 1.0, 4.0])
+def test_prefix_full_size(rs, kind, sigma):
+    P = 1 << 20
+    seed, inst = 4, 0
+    lw = workloads.normal_logweights(P, sigma, seed)
+    say(kind, "P=2^20 sigma", sigma)
+    anc_o, _, C_o = ORACLE_FN[kind](lw, seed, inst, want_cumw=True)
+    C = torch.empty(P, dtype=torch.float64, device="cuda")
+    anc_g = host(getattr(rs, f"resample_{kind}")(dev(lw), seed, inst, cumw=C))
+    worst = check_cumw(host(C), C_o)
+    n = explained_mismatches(kind, anc_g, anc_o, C_o, seed, inst)
+    say(f"  cumw worst rel {worst:.2e}, boundary mismatches {n}")
+    if kind != "multinomial":
+        assert np.all(np.diff(anc_g) >= 0)
+
+
+@pytest.mark.parametrize("kind", ["stratified", "systematic"])
+def test_prefix_heavy_particle_overflow_chunks(rs, kind):
+    # one particle carries almost all weight: its tile owns ~P outputs and is
+    # split over many fill blocks
+    P = 300000
+    lw = np.full(P, -40.0, dtype=np.float32)
+    lw[123457] = 0.0
+    lw[5] = -3.0
+    anc_o, _, C_o = ORACLE_FN[kind](lw, 2, 1, want_cumw=True)
+    C = torch.empty(P, dtype=torch.float64, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    anc_g = host(getattr(rs, f"resample_{kind}")(dev(lw), 2, 1, cumw=C, status=st))
+    assert int(host(st)[0]) == 0
+    check_cumw(host(C), C_o)
+    explained_mismatches(kind, anc_g, anc_o, C_o, 2, 1)
+
+
+@pytest.mark.parametrize("kind", PREFIX)
+def test_prefix_edge_weights(rs, kind):
+    fn = getattr(rs, f"resample_{kind}")
+    # equal weights: identity for stratified / systematic
+    P = 5000
+    eq = np.full(P, 1.5, dtype=np.float32)
+    anc_o, _ = ORACLE_FN[kind](eq, 1, 0)
+    anc_g = host(fn(dev(eq), 1, 0))
+    if kind != "multinomial":
+        assert np.array_equal(anc_g, np.arange(P))
+    assert np.array_equal(anc_g, anc_o)
+    # zero weights (-inf) inside, at the ends and filling whole tiles
+    lw = workloads.normal_logweights(6000, 1.0, 2)
+    lw[:5] = -np.inf
+    lw[1024:3072] = -np.inf
+    lw[-7:] = -np.inf
+    anc_o, _, C_o = ORACLE_FN[kind](lw, 3, 0, want_cumw=True)
+    C = torch.empty(lw.size, dtype=torch.float64, device="cuda")
+    anc_g = host(fn(dev(lw), 3, 0, cumw=C))
+    check_cumw(host(C), C_o)
+    explained_mismatches(kind, anc_g, anc_o, C_o, 3, 0)
+    assert np.all(np.isfinite(lw[anc_g])), "a zero-weight particle was selected"
+    # a single finite weight takes every draw
+    one = np.full(3000, -np.inf, dtype=np.float32)
+    one[2999] = 0.25
+    assert np.all(host(fn(dev(one), 1, 0)) == 2999)
+
+
+@pytest.mark.parametrize("kind", PREFIX)
+def test_prefix_flags(rs, kind):
+    fn = getattr(rs, f"resample_{kind}")
+    for bad, flag in ((np.nan, rs.FLAG_NAN), (np.inf, rs.FLAG_POSINF)):
+        lw = np.zeros(2500, dtype=np.float32)
+        lw[1700] = bad
+        st = torch.zeros(1, dtype=torch.int32, device="cuda")
+        anc = host(fn(dev(lw), 1, 0, status=st))
+        assert int(host(st)[0]) == flag
+        assert np.array_equal(anc, np.arange(2500))
+    lw = np.full(2500, -np.inf, dtype=np.float32)
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    anc = host(fn(dev(lw), 1, 0, status=st))
+    assert int(host(st)[0]) == rs.FLAG_ALL_NEGINF
+    # the workspace is clean again: a good call right after succeeds
+    lw = workloads.normal_logweights(2500, 1.0, 1)
+    st.zero_()
+    anc = host(fn(dev(lw), 1, 0, status=st))
+    assert int(host(st)[0]) == 0
+    anc_o, _ = ORACLE_FN[kind](lw, 1, 0)
+    assert np.count_nonzero(anc != anc_o) <= 2
+
+
+def test_prefix_deterministic_and_instances_differ(rs):
+    lw = dev(workloads.normal_logweights(200000, 1.0, 8))
+    for kind in PREFIX:
+        fn = getattr(rs, f"resample_{kind}")
+        a, b = host(fn(lw, 5, 1)), host(fn(lw, 5, 1))
+        assert np.array_equal(a, b)
+        c = host(fn(lw, 5, 2))
+        assert not np.array_equal(a, c)
+
+
+def test_log_sum_exp(rs):
+    for P, sigma in ((1, 1.0), (777, 2.0), (1 << 20, 4.0)):
+        lw = workloads.normal_logweights(P, sigma, 1)
+        C, m, _ = oracle.cumulative(lw)
+        ref = m + np.log(C[-1])
+        got = float(host(rs.rs_log_sum_exp(dev(lw)))[0])
+        assert abs(got - ref) <= 1e-12 * max(1.0, abs(ref))
+
+
+# ----------------------------------------------------------------- offspring, copy
+@pytest.mark.parametrize("P", [1, 63, 64, 65, 1000, 4097, 1 << 20])
+def test_offspring_bit_exact(rs, P):
+    rng = np.random.default_rng(P)
+    for anc in (rng.integers(0, P, P).astype(np.int32), np.sort(rng.integers(0, P, P)).astype(np.int32),
+                np.full(P, P // 2, dtype=np.int32)):
+        ref, _ = oracle.ancestors_to_offspring(anc)
+        assert np.array_equal(host(rs.ancestors_to_offspring(dev(anc))), ref)
+
+
+def test_offspring_bad_ancestor(rs):
+    anc = np.array([0, 1, 5, -1, 2, 2], dtype=np.int32)
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    off = host(rs.ancestors_to_offspring(dev(anc), status=st))
+    assert int(host(st)[0]) == rs.FLAG_BAD_ANCESTOR
+    assert np.array_equal(off, [1, 1, 2, 0, 0, 0])
+
+
+@pytest.mark.parametrize("P", [1, 5, 1023, 4096, 100003, 1 << 20])
+@pytest.mark.parametrize("D", [1, 3, 4, 8, 16])
+def test_permute_copy_bit_exact(rs, P, D):
+    if P == 1 << 20 and D not in (1, 4):
+        pytest.skip("full size covered for the D of the sweep")
+    rng = np.random.default_rng(D)
+    x = workloads.state_rows_exact(P, D)
+    x[rng.integers(0, P, min(P, 10))] = np.nan  # bits, not values
+    for anc in (rng.integers(0, P, P).astype(np.int32), np.sort(rng.integers(0, P, P)).astype(np.int32)):
+        ref, _ = oracle.permute_copy(anc, x)
+        out = host(rs.permute_copy(dev(anc), dev(x)))
+        assert np.array_equal(out.view(np.uint32), ref.view(np.uint32))
+
+
+def test_permute_copy_bad_ancestor_and_unaligned(rs):
+    P, D = 100, 4
+    x = workloads.state_rows_exact(P, D)
+    anc = np.arange(P, dtype=np.int32)[::-1].copy()
+    anc[7] = P
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    out = host(rs.permute_copy(dev(anc), dev(x), status=st))
+    assert int(host(st)[0]) == rs.FLAG_BAD_ANCESTOR
+    assert np.all(out[7] == 0)
+    ok = np.arange(P) != 7
+    assert np.array_equal(out[ok], x[anc[ok]])
+    # unaligned state pointers take the scalar path
+    big = dev(np.concatenate([np.zeros(1, np.float32), x.ravel()]))
+    out2 = torch.empty(P * D + 1, dtype=torch.float32, device="cuda")
+    anc[7] = 0
+    rs.permute_copy(dev(anc), big[1:], out2[1:])
+    assert np.array_equal(host(out2)[1:].reshape(P, D), x[anc])
+
+
+def test_binding_rejects_bad_tensors(rs):
+    from paper_1202_6163_amd._lib import ResampleError
+    lw = dev(np.zeros(10, np.float32))
+    with pytest.raises(TypeError):
+        rs.resample_metropolis(lw.double(), 4, 1)
+    with pytest.raises(ValueError):
+        rs.resample_metropolis(torch.zeros(10), 4, 1)
+    with pytest.raises(ValueError):
+        rs.resample_stratified(dev(np.zeros((4, 4), np.float32)).t(), 1)
+    ws = torch.zeros(8, dtype=torch.uint8, device="cuda")
+    with pytest.raises(ResampleError):
+        rs.resample_stratified(lw, 1, ws=ws)
