@@ -1,0 +1,386 @@
+"""Benchmark of the resampling stage on one MI355X.
+
+Step (the timed unit): one pass of the whole resampling path over one batch
+of P = 2^20 particles with log-weights N(0, sigma^2) (sigma = 1) and D = 4
+binary32 state rows: the Metropolis (B = 32), stratified, systematic and
+multinomial resamplers, each followed by the offspring conversion and the
+ancestor-indexed state copy. Every step uses the next of several rotating
+input/output buffer sets whose total exceeds the 256 MB Infinity Cache, so
+the step reads its inputs from HBM. value = resampled particles per second
+(4 P per step) at the p99 step time.
+
+Beside it the JSON line carries:
+  roofline      the dominant kernel of the step against its ceiling;
+  roofline_hbm  the stratified resample + state copy path against HBM;
+  sweep         per sigma and P, p50/p99 particles/s of every resampler
+                (Metropolis at each B), with and without the copy, the
+                accuracy metric sum_i (o_i/P - w_i/W)^2, the ESS, eq. (5)'s B
+                and the Metropolis-vs-stratified crossover (warm cache);
+  cpu_baseline  the CPU oracle on a bounded sample of the same step.
+"""
+import argparse
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# VALU issue rate from the unit counts: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
+VALU_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
+# Algorithmic VALU slots per Metropolis iteration: half a Philox4x32-10 block
+# (10 rounds x (two quarter-rate 32x32->64 multiplies + two 3-input xors)
+# / 2 = 50) plus the quarter-rate high-word multiply of the index map (4).
+METRO_SLOTS_PER_ITER = 54.0
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--P", type=int, default=1 << 20)
+    ap.add_argument("--D", type=int, default=4)
+    ap.add_argument("--sigma", type=float, default=1.0)
+    ap.add_argument("--B", type=int, default=32)
+    ap.add_argument("--sets", type=int, default=8, help="rotating buffer sets (cold HBM)")
+    ap.add_argument("--reps", type=int, default=40, help="timed calls per sweep point")
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--sweep-P", type=str, default="12,14,16,18,20")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--only", type=str, default="", help="time one kernel (for profiling)")
+    ap.add_argument("--out", type=str, default="")
+    return ap.parse_args()
+
+
+def pct(a, q):
+    return float(np.percentile(np.asarray(a), q))
+
+
+class Graphs:
+    """Calls captured into HIP graphs (torch.cuda.CUDAGraph on the library's
+    stream) and replayed back to back with a HIP event between replays, so the
+    GPU never waits for the host: interval k = replay k's GPU time."""
+
+    def __init__(self, torch):
+        self.torch = torch
+
+    def capture(self, fn):
+        torch = self.torch
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            fn()  # warm-up outside the capture (sets kernel attributes)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            fn()
+        torch.cuda.synchronize()
+        return g
+
+    def replay_ms(self, graphs, n):
+        """Replay graphs[k % len] for k < n; returns the n intervals in ms."""
+        torch = self.torch
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
+        graphs[0].replay()  # prime the queue so the first interval is GPU-bound
+        ev[0].record()
+        for k in range(n):
+            graphs[k % len(graphs)].replay()
+            ev[k + 1].record()
+        torch.cuda.synchronize()
+        return [ev[k].elapsed_time(ev[k + 1]) for k in range(n)]
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU sharding is "
+                                   "design-only (see DESIGN.md)", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+
+    import paper_1202_6163_amd.api as rs
+    from paper_1202_6163_amd import workloads
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    torch.cuda.set_device(0)
+    P, D, B, sigma = args.P, args.D, args.B, args.sigma
+    dev = torch.device("cuda", 0)
+
+    # ------------------------------------------------ rotating cold buffer sets
+    sets = []
+    for s in range(args.sets):
+        lw = torch.from_numpy(workloads.normal_logweights(P, sigma, s)).to(dev)
+        x = torch.from_numpy(workloads.state_rows_normal(P, D, s)).to(dev)
+        sets.append(dict(lw=lw, x=x, anc=torch.empty(P, dtype=torch.int32, device=dev),
+                         off=torch.empty(P, dtype=torch.int32, device=dev),
+                         xo=torch.empty_like(x)))
+    ws = rs.workspace(P, rs.MULTINOMIAL, dev)
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    set_bytes = sum(t.numel() * t.element_size() for t in sets[0].values())
+
+    def step(bs, seed, inst):
+        for name, fn in (("metropolis", None), ("stratified", rs.resample_stratified),
+                         ("systematic", rs.resample_systematic),
+                         ("multinomial", rs.resample_multinomial)):
+            if fn is None:
+                rs.resample_metropolis(bs["lw"], B, seed, inst, anc=bs["anc"], status=status)
+            else:
+                fn(bs["lw"], seed, inst, anc=bs["anc"], ws=ws, status=status)
+            rs.ancestors_to_offspring(bs["anc"], off=bs["off"], status=status)
+            rs.permute_copy(bs["anc"], bs["x"], x_out=bs["xo"], status=status)
+
+    if args.only:
+        # profiling mode: plain launches of one kernel family on the cold sets
+        only = {"metropolis": lambda bs, k: rs.resample_metropolis(bs["lw"], B, k, 0, anc=bs["anc"]),
+                "stratified": lambda bs, k: rs.resample_stratified(bs["lw"], k, 0, anc=bs["anc"], ws=ws),
+                "copy": lambda bs, k: rs.permute_copy(bs["anc"], bs["x"], x_out=bs["xo"]),
+                "step": lambda bs, k: step(bs, k, 0)}[args.only]
+        for bs in sets:
+            rs.resample_stratified(bs["lw"], 1, 0, anc=bs["anc"], ws=ws)
+        for k in range(args.warmup + args.steps):
+            only(sets[k % len(sets)], k)
+        torch.cuda.synchronize()
+        print(f"profiled {args.only}: {args.warmup + args.steps} calls", flush=True)
+        return
+
+    G = Graphs(torch)
+    step_graphs = [G.capture(lambda bs=bs, k=k: step(bs, 1000 + k, 0)) for k, bs in enumerate(sets)]
+    G.replay_ms(step_graphs, max(args.warmup, 1))
+
+    # ------------------------------------------------ timed steps (cold)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    step_ms = G.replay_ms(step_graphs, args.steps)
+    wall = time.perf_counter() - t0
+    assert int(status.item()) == 0, f"status flags {int(status.item())}"
+    p99 = pct(step_ms, 99)
+    value = 4 * P / (p99 * 1e-3)
+
+    # ------------------------------------------------ per-kernel rooflines (cold)
+    def time_calls(fn, per_graph=None, replays=8):
+        """Mean GPU time of one call: graphs of one call per buffer set."""
+        n_sets = len(sets)
+        g = G.capture(lambda: [fn(bs, k) for k, bs in enumerate(sets)])
+        ms = G.replay_ms([g], replays)
+        return [m / n_sets for m in ms]
+
+    for bs in sets:  # sorted ancestors for the copy
+        rs.resample_stratified(bs["lw"], 7, 0, anc=bs["anc"], ws=ws)
+    copy_ms = time_calls(lambda bs, k: rs.permute_copy(bs["anc"], bs["x"], x_out=bs["xo"]))
+    strat_ms = time_calls(lambda bs, k: rs.resample_stratified(bs["lw"], k, 0, anc=bs["anc"], ws=ws))
+    metro_ms = time_calls(lambda bs, k: rs.resample_metropolis(bs["lw"], B, k, 0, anc=bs["anc"]))
+    multi_ms = time_calls(lambda bs, k: rs.resample_multinomial(bs["lw"], k, 0, anc=bs["anc"], ws=ws))
+    syst_ms = time_calls(lambda bs, k: rs.resample_systematic(bs["lw"], k, 0, anc=bs["anc"], ws=ws))
+    # the copy above used sorted ancestors; the sweep reports unsorted ones too
+    for bs in sets:
+        rs.resample_stratified(bs["lw"], 7, 0, anc=bs["anc"], ws=ws)
+    means = {"metropolis": np.mean(metro_ms), "stratified": np.mean(strat_ms),
+             "systematic": np.mean(syst_ms), "multinomial": np.mean(multi_ms),
+             "permute_copy": np.mean(copy_ms)}
+    dominant = max(means, key=means.get)
+    iters = float(P) * B
+    traffic = load_traffic(dominant)
+    if dominant == "metropolis":
+        achieved = iters * METRO_SLOTS_PER_ITER / (means["metropolis"] * 1e-3) / 1e12
+        peak = VALU_SLOTS_PER_S / 1e12
+        roofline = {"bound": "alu", "achieved": achieved, "peak": peak,
+                    "unit": "TVALU-slot/s", "frac": achieved / peak, "traffic": traffic,
+                    "kernel": "metropolis_kernel", "avg_launch_us": means["metropolis"] * 1e3,
+                    "units_per_launch": {"chain_iterations": iters},
+                    "algorithmic_per_unit": {"valu_slots": METRO_SLOTS_PER_ITER}}
+    else:
+        per = {"stratified": 12, "systematic": 12, "multinomial": 24,
+               "permute_copy": 4 + 8 * D}[dominant]
+        achieved = per * P / (means[dominant] * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dominant,
+                    "avg_launch_us": means[dominant] * 1e3}
+    copy_gbs = (4 + 8 * D) * P / (np.mean(copy_ms) * 1e-3) / 1e9
+    strat_gbs = 12 * P / (np.mean(strat_ms) * 1e-3) / 1e9
+    path_gbs = (12 + 4 + 8 * D) * P / ((np.mean(copy_ms) + np.mean(strat_ms)) * 1e-3) / 1e9
+    roofline_hbm = {
+        "bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "permute_copy": {"achieved": copy_gbs, "frac": copy_gbs / HBM_PEAK_GBS,
+                         "bytes_per_particle": 4 + 8 * D, "avg_launch_us": np.mean(copy_ms) * 1e3},
+        "stratified": {"achieved": strat_gbs, "frac": strat_gbs / HBM_PEAK_GBS,
+                       "bytes_per_particle": 12, "avg_call_us": np.mean(strat_ms) * 1e3,
+                       "launches": 2},
+        "stratified_plus_copy": {"achieved": path_gbs, "frac": path_gbs / HBM_PEAK_GBS,
+                                 "bytes_per_particle": 16 + 8 * D},
+    }
+
+    out = {
+        "metric": "resampled particles/s at P=2^20 (Metropolis B vs stratified) by weight var; p99",
+        "value": value, "unit": "particles/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": float(np.mean(step_ms)),
+        "p50_ms_per_step": pct(step_ms, 50), "p99_ms_per_step": p99,
+        "wall_s_timed": wall, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 weights / f64 prefix sums / u32 Philox",
+        "data": "synthetic", "config": {
+            "workload": "resampler sweep point P=2^20, lw ~ N(0, 1), D=4 state copy; step = "
+                        "Metropolis(B=32) + stratified + systematic + multinomial, each with "
+                        "offspring + copy; cold HBM (rotating buffer sets)",
+            "P": P, "D": D, "sigma": sigma, "B": B, "buffer_sets": args.sets,
+            "set_bytes": set_bytes, "parallelism": "single GPU"},
+        "per_call_ms_cold": {k: float(v) for k, v in means.items()},
+        "roofline": roofline, "roofline_hbm": roofline_hbm,
+        "device": torch.cuda.get_device_name(0),
+    }
+    if not args.no_sweep:
+        out["sweep"] = sweep(torch, rs, workloads, args)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args, workloads)
+    line = json.dumps(out)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(line + "\n")
+    print(line, flush=True)
+
+
+def load_traffic(kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources (null otherwise)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    entry = rec.get(kernel)
+    if not entry or entry.get("source_sha256") != source_hash():
+        return None
+    return entry.get("bytes_per_launch")
+
+
+def source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1202_6163_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + f.read())
+    return h.hexdigest()
+
+
+def sweep(torch, rs, workloads, args):
+    """Warm-cache p50/p99 particles/s per (P, sigma, resampler[, B]), accuracy
+    metric, ESS, eq. (5) B and the Metropolis-vs-stratified crossover."""
+    dev = torch.device("cuda", 0)
+    G = Graphs(torch)
+    res = {"note": "warm cache (buffers reused); per-call time = a graph replay of R "
+                   "back-to-back calls / R; p50/p99 over replays", "points": []}
+    Ps = [1 << int(v) for v in args.sweep_P.split(",") if v]
+    D = args.D
+    for P in Ps:
+        ws = rs.workspace(P, rs.MULTINOMIAL, dev)
+        x = torch.from_numpy(workloads.state_rows_normal(P, D, 0)).to(dev)
+        xo = torch.empty_like(x)
+        anc = torch.empty(P, dtype=torch.int32, device=dev)
+        off = torch.empty(P, dtype=torch.int32, device=dev)
+        for sigma in workloads.SIGMAS:
+            lw = torch.from_numpy(workloads.normal_logweights(P, sigma, 0)).to(dev)
+            w = torch.exp(lw.double() - lw.max().double())
+            W = w.sum()
+            p = (w / W)
+            ess = float(1.0 / (p * p).sum())
+            wmax = float(p.max())
+            point = {"P": P, "sigma": sigma, "ess_frac": ess / P,
+                     "B_eq5_eps1e-2": rs.metropolis_B(P, wmax, 1e-2),
+                     "B_eq5_eps1e-3": rs.metropolis_B(P, wmax, 1e-3), "resamplers": {}}
+
+            def measure(call, with_copy):
+                R = max(1, min(64, int(2e5 // P) + 1))  # calls per graph (>= ~50 us of work)
+
+                def body():
+                    for k in range(R):
+                        call(k)
+                        if with_copy:
+                            rs.permute_copy(anc, x, x_out=xo)
+                g = G.capture(body)
+                ms = [m / R for m in G.replay_ms([g], args.reps)]
+                return {"p50_pps": P / (pct(ms, 50) * 1e-3), "p99_pps": P / (pct(ms, 99) * 1e-3),
+                        "p50_us": pct(ms, 50) * 1e3, "p99_us": pct(ms, 99) * 1e3,
+                        "calls_per_graph": R}
+
+            def accuracy(call):
+                errs = []
+                for s in range(4):
+                    call(100 + s)
+                    rs.ancestors_to_offspring(anc, off=off)
+                    e = ((off.double() / P - p) ** 2).sum()
+                    errs.append(float(e))
+                return float(np.mean(errs))
+
+            calls = {"stratified": lambda k: rs.resample_stratified(lw, k, 0, anc=anc, ws=ws),
+                     "systematic": lambda k: rs.resample_systematic(lw, k, 0, anc=anc, ws=ws),
+                     "multinomial": lambda k: rs.resample_multinomial(lw, k, 0, anc=anc, ws=ws)}
+            for Bm in workloads.SWEEP_B:
+                calls[f"metropolis_B{Bm}"] = (
+                    lambda k, Bm=Bm: rs.resample_metropolis(lw, Bm, k, 0, anc=anc))
+            for name, call in calls.items():
+                r = measure(call, False)
+                r["with_copy"] = measure(call, True)
+                r["error"] = accuracy(call)
+                point["resamplers"][name] = r
+            strat = point["resamplers"]["stratified"]["p99_pps"]
+            faster = [Bm for Bm in workloads.SWEEP_B
+                      if point["resamplers"][f"metropolis_B{Bm}"]["p99_pps"] > strat]
+            point["metropolis_faster_up_to_B"] = max(faster) if faster else 0
+            need = point["B_eq5_eps1e-2"]
+            point["metropolis_converged_faster"] = bool(faster) and need <= max(faster)
+            res["points"].append(point)
+            print(f"sweep P={P} sigma={sigma}: stratified {strat:.3e} p/s, Metropolis faster up "
+                  f"to B={point['metropolis_faster_up_to_B']}, eq5 B={need}", file=sys.stderr,
+                  flush=True)
+    cross = {}
+    for P in Ps:
+        pts = [q for q in res["points"] if q["P"] == P]
+        wins = [q["sigma"] for q in pts if q["metropolis_converged_faster"]]
+        cross[str(P)] = max(wins) if wins else None
+    res["crossover_sigma_by_P"] = cross
+    res["crossover_note"] = ("largest swept sigma at which Metropolis with the eq. (5) B "
+                             "(eps = 0.01, rounded up to the swept B grid) is faster than "
+                             "stratified at p99; null: never")
+    return res
+
+
+def cpu_baseline(args, workloads):
+    """The oracle (single-threaded C, as committed) on a bounded sample of the
+    step: the same four resamplers + offspring + copy at P = 2^20, timed over
+    whole steps until about --cpu-seconds of CPU time."""
+    import oracle
+    P, D, B = args.P, args.D, args.B
+    lw = workloads.normal_logweights(P, args.sigma, 0)
+    x = workloads.state_rows_normal(P, D, 0)
+    times = []
+    t_start = time.perf_counter()
+    while True:
+        t0 = time.perf_counter()
+        for kind in ("metropolis", "stratified", "systematic", "multinomial"):
+            if kind == "metropolis":
+                anc, _ = oracle.metropolis(lw, B, 1, 0)
+            else:
+                anc, _ = getattr(oracle, kind)(lw, 1, 0)
+            oracle.ancestors_to_offspring(anc)
+            oracle.permute_copy(anc, x)
+        times.append(time.perf_counter() - t0)
+        if time.perf_counter() - t_start > args.cpu_seconds or len(times) >= 20:
+            break
+    t = float(np.mean(times))
+    return {"value": 4 * P / t, "unit": "particles/s", "cores": 1, "kind": "oracle",
+            "sample": f"{len(times)} full steps at P=2^20 (4 resamplers + offspring + copy, "
+                      f"Metropolis B={B}), single-threaded C oracle",
+            "seconds_per_step": t, "host_cpu": platform.processor() or platform.machine(),
+            "host_nproc": os.cpu_count()}
+
+
+if __name__ == "__main__":
+    main()

@@ -71,16 +71,16 @@ int rs_version(void);
 
 /*
  * Bytes of workspace the prefix-sum resamplers need for P particles: tile
- * partial sums, tile boundaries, a completion counter and, for the
- * multinomial resampler, the cumulative weights (pooled temporaries; Sec. 3
- * replaces per-call allocations with reused pooled arrays). 0 for
- * RS_METROPOLIS. The workspace must be zero-filled before its first use
- * (rs_workspace_init or any zero fill); every call leaves it reusable.
+ * partial sums, tile boundaries, per-tile draw counts, the fill table and,
+ * for the multinomial resampler, the cumulative weights (pooled temporaries;
+ * Sec. 3 replaces per-call allocations with reused pooled arrays). 0 for
+ * RS_METROPOLIS. The workspace needs no initialisation: every call writes
+ * what it reads, so one buffer serves any sequence of ordered calls.
  */
 size_t rs_workspace_bytes(int64_t P, int resampler);
 
-/* Zero-fill a workspace [device] of ws_bytes bytes on `stream` (a kernel, no
- * memset node). */
+/* Zero-fill ws_bytes bytes of device memory on `stream` with a kernel (no
+ * memset node, so it may be captured in a graph). Optional for workspaces. */
 int rs_workspace_init(void *ws, size_t ws_bytes, hipStream_t stream);
 
 /*
