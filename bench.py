@@ -55,6 +55,10 @@ def parse():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--sweep-P", type=str, default="12,14,16,18,20")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-filter", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="seconds of Poisson arrivals at 2000 req/s (0: skip; the full run is 60)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--only", type=str, default="", help="time one kernel (for profiling)")
     ap.add_argument("--out", type=str, default="")
@@ -238,6 +242,12 @@ def main():
     }
     if not args.no_sweep:
         out["sweep"] = sweep(torch, rs, workloads, args)
+    if not args.no_batch:
+        out["batched"] = batched(torch, rs, workloads, args)
+    if not args.no_filter:
+        out["filter"] = filter_run(torch, workloads, args)
+    if args.serve_seconds > 0:
+        out["serving"] = serving(torch, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, workloads)
     line = json.dumps(out)
@@ -350,6 +360,91 @@ def sweep(torch, rs, workloads, args):
                              "(eps = 0.01, rounded up to the swept B grid) is faster than "
                              "stratified at p99; null: never")
     return res
+
+
+def batched(torch, rs, workloads, args):
+    """1024 instances, P log-uniform in [2^8, 2^16], sigma in [0.25, 3],
+    Metropolis B = 64 and stratified alternating, D = 16: one batched graph
+    replay against the same work as per-instance calls (resample +
+    permute_copy) captured in one graph, and launched one by one."""
+    from paper_1202_6163_amd.batch import Batch
+    dev = torch.device("cuda", 0)
+    P, sig = workloads.batch_instances(1024, seed=0)
+    insts = []
+    for k in range(len(P)):
+        Pk = int(P[k])
+        insts.append(dict(
+            lw=torch.from_numpy(workloads.normal_logweights(Pk, sig[k], k)).to(dev),
+            anc=torch.empty(Pk, dtype=torch.int32, device=dev),
+            kind="metropolis" if k % 2 else "stratified", B=64, seed=5, instance=k,
+            x_in=torch.from_numpy(workloads.state_rows_normal(Pk, 16, k)).to(dev),
+            x_out=torch.empty((Pk, 16), dtype=torch.float32, device=dev)))
+    total = int(P.sum())
+    G = Graphs(torch)
+    b = Batch(insts)
+    gb = G.capture(b.run)
+    ms_b = G.replay_ms([gb], 10)
+    ws = rs.workspace(1 << 16, rs.STRATIFIED, dev)
+
+    def per_instance():
+        for d in insts:
+            if d["kind"] == "metropolis":
+                rs.resample_metropolis(d["lw"], d["B"], d["seed"], d["instance"], anc=d["anc"])
+            else:
+                rs.resample_stratified(d["lw"], d["seed"], d["instance"], anc=d["anc"], ws=ws)
+            rs.permute_copy(d["anc"], d["x_in"], x_out=d["x_out"])
+    gp = G.capture(per_instance)
+    ms_p = G.replay_ms([gp], 5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    per_instance()
+    torch.cuda.synchronize()
+    eager_ms = (time.perf_counter() - t0) * 1e3
+    tb, tp = pct(ms_b, 50), pct(ms_p, 50)
+    return {"instances": len(P), "particles": total, "D": 16,
+            "batched_ms_p50": tb, "batched_ms_p99": pct(ms_b, 99),
+            "per_instance_graph_ms_p50": tp, "per_instance_eager_ms": eager_ms,
+            "batched_instances_per_s": len(P) / (tb * 1e-3),
+            "batched_particles_per_s": total / (tb * 1e-3),
+            "per_instance_graph_particles_per_s": total / (tp * 1e-3),
+            "speedup_vs_per_instance_graph": tp / tb, "speedup_vs_eager": eager_ms / tb,
+            "tuning": dict(chains_per_item=b.tuning.chains_per_item, unroll=b.tuning.unroll,
+                           lds_max_p=b.tuning.lds_max_p, blocks=b.plan.blocks)}
+
+
+def filter_run(torch, workloads, args):
+    """Bootstrap filter, D = 8, T = 200, P = 2^18, stratified resampling every
+    step, one HIP graph per run; log-likelihood against the Kalman filter."""
+    from oracle.kalman import kalman_loglik
+    from paper_1202_6163_amd.filter import BootstrapFilter
+    A = workloads.filter_model(D=8, seed=0)
+    y = workloads.filter_observations(A, T=200, seed=0)
+    ll_true = kalman_loglik(A, y, 0.1, 0.5)
+    res = {"P": 1 << 18, "D": 8, "T": 200, "kalman_loglik": ll_true}
+    for resampler in ("stratified", "metropolis"):
+        f = BootstrapFilter(A, 1 << 18, seed=1, resampler=resampler, B=64)
+        yd = torch.as_tensor(y, device="cuda")
+        lse = torch.empty(200, dtype=torch.float64, device="cuda")
+        g = f.capture(yd, lse)
+        G = Graphs(torch)
+        ms = G.replay_ms([g], 5)
+        res[resampler] = {"ms_per_run_p50": pct(ms, 50), "us_per_step": pct(ms, 50) * 1e3 / 200,
+                          "loglik": f.loglik(lse)}
+    return res
+
+
+def serving(torch, args):
+    """Poisson arrivals at 2000 req/s, P log-uniform in [2^10, 2^20], sigma in
+    [0.5, 4], D in {1, 16}, Metropolis B = 64 or stratified, resident on the
+    device, admitted by footprint, continuously batched on 4 streams."""
+    from paper_1202_6163_amd.serve import GpuExecutor, make_requests, serve, summarize
+    reqs = make_requests(rate=2000.0, duration=args.serve_seconds, seed=0)
+    ex = GpuExecutor(n_streams=4)
+    sched = serve(reqs, ex, budget_bytes=32 << 30, max_batch=256)
+    s = summarize(sched, args.serve_seconds)
+    s.update({"rate_req_per_s": 2000.0, "seconds": args.serve_seconds,
+              "budget_bytes": 32 << 30, "streams": 4})
+    return s
 
 
 def cpu_baseline(args, workloads):

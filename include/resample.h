@@ -62,12 +62,16 @@ typedef struct ihipStream_t *hipStream_t;
 #define RS_MULTINOMIAL 2
 #define RS_METROPOLIS 3
 #define RS_LOG_SUM_EXP 4
+#define RS_METROPOLIS_ADAPTIVE 5
 
 /* Human-readable name of a return code. Never NULL. */
 const char *rs_strerror(int code);
 
 /* Library version as 10000 * major + 100 * minor + patch. */
 int rs_version(void);
+
+/* Description of the HIP error behind the calling thread's last RS_EHIP. */
+const char *rs_last_hip_error(void);
 
 /*
  * Bytes of workspace the prefix-sum resamplers need for P particles: tile
@@ -95,6 +99,23 @@ int rs_workspace_init(void *ws, size_t ws_bytes, hipStream_t stream);
  */
 int resample_metropolis(const float *lw, int32_t *anc, int64_t P, uint32_t B, uint64_t seed,
                         uint32_t instance, int32_t *status, hipStream_t stream);
+
+/*
+ * Metropolis resampler with B chosen per call from the weights (Sec. 2:
+ * eq. (5) for the largest normalised weight w_max and tolerance eps; the
+ * paper warns that too small a B biases the sample). A tile reduction and a
+ * one-block table compute W = sum_i exp(lw_i - max lw), so w_max = 1 / W,
+ * and B = min(eq. (5), B_max) on the device; the chain kernel then reads B
+ * from device memory (no host round trip; graph-capturable).
+ *   eps    > 0; B_max caps the iteration count
+ *   ws     [device] workspace of ws_bytes >= rs_workspace_bytes(P, RS_METROPOLIS_ADAPTIVE)
+ *   B_used [device] uint32[1], nullable: the B that was used
+ * Same results as resample_metropolis with that B.
+ */
+int resample_metropolis_adaptive(const float *lw, int32_t *anc, int64_t P, double eps,
+                                 uint32_t B_max, uint64_t seed, uint32_t instance, void *ws,
+                                 size_t ws_bytes, uint32_t *B_used, int32_t *status,
+                                 hipStream_t stream);
 
 /*
  * Stratified resampler (Sec. 2, Fig. 1(b)): one uniform draw in each stratum
@@ -149,6 +170,102 @@ int permute_copy(const int32_t *anc, const float *x_in, float *x_out, int64_t P,
  */
 int rs_log_sum_exp(const float *lw, int64_t P, double *out, void *ws, size_t ws_bytes,
                    int32_t *status, hipStream_t stream); /* P >= 1 */
+
+/*
+ * Batched resampling: many independent instances of uneven size in one graph
+ * replay of three persistent launches (tile reductions, per-instance tables,
+ * then Metropolis chains and stratified/systematic fills with the state copy
+ * fused in). Particle MCMC runs many filters, each resampling at every step
+ * (Sec. 1); batching removes the per-instance launch overhead the paper
+ * observes for small resamplings (Sec. 3). Every instance's ancestors and
+ * copied rows are bit-identical to the corresponding single call
+ * (resample_metropolis / resample_stratified / resample_systematic, then
+ * permute_copy) with the same seed and instance.
+ *
+ * Usage: fill rs_instance[n] on the host; size the device plan and workspace
+ * with rs_batch_plan_bytes / rs_batch_workspace_bytes; rs_batch_plan_init
+ * validates the instances, builds the work lists and uploads them; then
+ * resample_batch (any number of times, capturable in a graph) runs them.
+ */
+typedef struct rs_instance {
+    const float *lw;    /* [device] float[P] log-weights */
+    int32_t *anc;       /* [device] int32[P] ancestors (output) */
+    const float *x_in;  /* [device] float[P x D] state, or NULL: no copy */
+    float *x_out;       /* [device] float[P x D] copied state (output) */
+    int32_t *status;    /* [device] int32[1] flags of this instance, nullable */
+    int64_t P;          /* 0 <= P <= 2^31 - 1 */
+    int32_t D;          /* state width when x_in != NULL (>= 1) */
+    int32_t kind;       /* RS_METROPOLIS, RS_STRATIFIED or RS_SYSTEMATIC */
+    uint32_t B;         /* Metropolis iterations */
+    uint32_t instance;  /* Philox instance word */
+    uint64_t seed;      /* Philox key */
+} rs_instance;
+
+typedef struct rs_batch_tuning {
+    int32_t chains_per_item; /* Metropolis chains per work item: 256, 512, 1024 or 2048 */
+    int32_t unroll;          /* Metropolis iterations per round: 2, 4, 8 or 16 */
+    int64_t lds_max_p;       /* stage an instance's weights in LDS when P <= this (<= 32768) */
+    int32_t blocks;          /* persistent blocks per launch; 0 = 8 per compute unit */
+} rs_batch_tuning;
+
+/* Filled by rs_batch_plan_init; plain data (device pointers and counts). */
+typedef struct rs_batch_plan {
+    const void *dev;           /* device plan buffer */
+    int32_t n_instances;
+    int32_t n_tile_items;
+    int32_t n_table_items;
+    int32_t n_main_items;
+    int32_t blocks;
+    int32_t unroll;
+    int32_t chains_per_item;
+    int32_t reserved;
+    int64_t lds_max_p;
+    int64_t max_table_tiles;
+    uint64_t off_tile_items;   /* byte offsets inside dev */
+    uint64_t off_table_items;
+    uint64_t off_main_items;
+    uint64_t smem_main;
+} rs_batch_plan;
+
+/* Device bytes of the plan buffer (descriptors + work lists); 0 if invalid.
+ * t may be NULL for the defaults. */
+size_t rs_batch_plan_bytes(const rs_instance *descs, int32_t n, const rs_batch_tuning *t);
+/* Device bytes of workspace for the batch's stratified/systematic instances. */
+size_t rs_batch_workspace_bytes(const rs_instance *descs, int32_t n);
+/*
+ * Validate descs[n] (host array), build the work lists and copy them to
+ * plan_dev (device, plan_bytes >= rs_batch_plan_bytes). ws (device,
+ * ws_bytes >= rs_batch_workspace_bytes) is carved into per-instance
+ * workspaces. With host_staging == NULL the upload is synchronous on
+ * `stream`; otherwise host_staging (pinned host memory of plan_bytes bytes)
+ * receives the plan and is copied asynchronously on `stream`, and must stay
+ * untouched until that copy completes. Errors: RS_EINVAL (bad instance or
+ * tuning), RS_EWORKSPACE (plan_bytes or ws_bytes too small), RS_EHIP.
+ */
+int rs_batch_plan_init(rs_batch_plan *plan, const rs_instance *descs, int32_t n,
+                       const rs_batch_tuning *t, void *plan_dev, size_t plan_bytes, void *ws,
+                       size_t ws_bytes, void *host_staging, hipStream_t stream);
+/* Run a batch (asynchronous on `stream`; graph-capturable). */
+int resample_batch(const rs_batch_plan *plan, hipStream_t stream);
+
+/*
+ * Bootstrap particle filter around the resampler (Sec. 1: initialisation,
+ * propagation, weighting) for the linear-Gaussian model
+ *   x_0 ~ N(0, I),  x_t = A x_{t-1} + N(0, q I),  y_t = x_t + N(0, r I),
+ * with the transition as proposal, so lw_i = log N(y_t; x_t^i, r I).
+ * Gaussian draws: Box-Muller on Philox block (i, t, h, 5) for components
+ * 4h..4h+3, u1 = (r + 1/2) 2^-32, u2 = r' 2^-32 (t = 0: initial state).
+ *   x, x_in, x_out [device] float[P x D] row-major, 1 <= D <= 64; x_in and
+ *                  x_out must not overlap
+ *   lw             [device] float[P] log-weights (output)
+ *   A              [device] double[D x D] row-major transition matrix
+ *   y              [device] float[D] observation at time t
+ *   q, r           noise variances (q >= 0, r > 0); t >= 1 for a step
+ */
+int filter_init(float *x, int64_t P, int32_t D, uint64_t seed, hipStream_t stream);
+int filter_propagate_weight(const float *x_in, float *x_out, float *lw, int64_t P, int32_t D,
+                            const double *A, const float *y, double q, double r, uint64_t seed,
+                            uint32_t t, hipStream_t stream);
 
 /*
  * Number of Metropolis iterations B (Sec. 2, eqs. (1)-(5)) for P particles

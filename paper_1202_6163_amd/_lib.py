@@ -18,12 +18,35 @@ HEADER = os.path.join(ROOT, "include", "resample.h")
 
 RS_OK, RS_EINVAL, RS_EWORKSPACE, RS_EHIP = 0, -1, -2, -3
 FLAG_NAN, FLAG_POSINF, FLAG_ALL_NEGINF, FLAG_BAD_ANCESTOR, FLAG_INTERNAL = 1, 2, 4, 8, 16
-STRATIFIED, SYSTEMATIC, MULTINOMIAL, METROPOLIS, LOG_SUM_EXP = 0, 1, 2, 3, 4
+STRATIFIED, SYSTEMATIC, MULTINOMIAL, METROPOLIS, LOG_SUM_EXP, METROPOLIS_ADAPTIVE = 0, 1, 2, 3, 4, 5
 
 
 class Tuning(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("unroll", ctypes.c_int32),
                 ("lds_max_p", ctypes.c_int64), ("lanes_per_chain", ctypes.c_int32)]
+
+
+class Instance(ctypes.Structure):
+    _fields_ = [("lw", ctypes.c_void_p), ("anc", ctypes.c_void_p), ("x_in", ctypes.c_void_p),
+                ("x_out", ctypes.c_void_p), ("status", ctypes.c_void_p), ("P", ctypes.c_int64),
+                ("D", ctypes.c_int32), ("kind", ctypes.c_int32), ("B", ctypes.c_uint32),
+                ("instance", ctypes.c_uint32), ("seed", ctypes.c_uint64)]
+
+
+class BatchTuning(ctypes.Structure):
+    _fields_ = [("chains_per_item", ctypes.c_int32), ("unroll", ctypes.c_int32),
+                ("lds_max_p", ctypes.c_int64), ("blocks", ctypes.c_int32)]
+
+
+class BatchPlan(ctypes.Structure):
+    _fields_ = [("dev", ctypes.c_void_p), ("n_instances", ctypes.c_int32),
+                ("n_tile_items", ctypes.c_int32), ("n_table_items", ctypes.c_int32),
+                ("n_main_items", ctypes.c_int32), ("blocks", ctypes.c_int32),
+                ("unroll", ctypes.c_int32), ("chains_per_item", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("lds_max_p", ctypes.c_int64),
+                ("max_table_tiles", ctypes.c_int64), ("off_tile_items", ctypes.c_uint64),
+                ("off_table_items", ctypes.c_uint64), ("off_main_items", ctypes.c_uint64),
+                ("smem_main", ctypes.c_uint64)]
 
 
 def header_functions():
@@ -44,10 +67,13 @@ def _load():
     sig = {
         "rs_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "rs_version": (ctypes.c_int, []),
+        "rs_last_hip_error": (ctypes.c_char_p, []),
         "rs_workspace_bytes": (sz, [i64, ctypes.c_int]),
         "rs_workspace_init": (ctypes.c_int, [vp, sz, vp]),
         "resample_metropolis": (ctypes.c_int, [vp, vp, i64, u32, u64, u32, i32p, vp]),
         "resample_stratified": (ctypes.c_int, [vp, vp, i64, u64, u32, vp, vp, sz, i32p, vp]),
+        "resample_metropolis_adaptive": (ctypes.c_int, [vp, vp, i64, ctypes.c_double, u32, u64,
+                                                        u32, vp, sz, vp, i32p, vp]),
         "resample_systematic": (ctypes.c_int, [vp, vp, i64, u64, u32, vp, vp, sz, i32p, vp]),
         "resample_multinomial": (ctypes.c_int, [vp, vp, i64, u64, u32, vp, vp, sz, i32p, vp]),
         "ancestors_to_offspring": (ctypes.c_int, [vp, vp, i64, i32p, vp]),
@@ -55,7 +81,18 @@ def _load():
         "rs_log_sum_exp": (ctypes.c_int, [vp, i64, vp, vp, sz, i32p, vp]),
         "metropolis_B": (u32, [i64, ctypes.c_double, ctypes.c_double]),
         "rs_log_u_table": (ctypes.c_int, [vp, vp, vp]),
+        "filter_init": (ctypes.c_int, [vp, i64, ctypes.c_int32, u64, vp]),
+        "filter_propagate_weight": (ctypes.c_int, [vp, vp, vp, i64, ctypes.c_int32, vp, vp,
+                                                   ctypes.c_double, ctypes.c_double, u64, u32,
+                                                   vp]),
         "rs_metropolis_set_tuning": (ctypes.c_int, [ctypes.POINTER(Tuning)]),
+        "rs_batch_plan_bytes": (sz, [ctypes.POINTER(Instance), ctypes.c_int32,
+                                     ctypes.POINTER(BatchTuning)]),
+        "rs_batch_workspace_bytes": (sz, [ctypes.POINTER(Instance), ctypes.c_int32]),
+        "rs_batch_plan_init": (ctypes.c_int, [ctypes.POINTER(BatchPlan), ctypes.POINTER(Instance),
+                                              ctypes.c_int32, ctypes.POINTER(BatchTuning), vp, sz,
+                                              vp, sz, vp, vp]),
+        "resample_batch": (ctypes.c_int, [ctypes.POINTER(BatchPlan), vp]),
         "rs_metropolis_get_tuning": (ctypes.c_int, [ctypes.POINTER(Tuning)]),
     }
     for name, (res, args) in sig.items():
@@ -74,5 +111,6 @@ class ResampleError(RuntimeError):
 
 def check(rc, what):
     if rc != RS_OK:
-        raise ResampleError(f"{what}: {lib.rs_strerror(rc).decode()} (rc={rc})")
+        detail = f" [{lib.rs_last_hip_error().decode()}]" if rc == RS_EHIP else ""
+        raise ResampleError(f"{what}: {lib.rs_strerror(rc).decode()} (rc={rc}){detail}")
     return rc

@@ -88,6 +88,25 @@ def resample_metropolis(lw, B, seed, instance=0, anc=None, status=None, stream=N
     return anc
 
 
+def resample_metropolis_adaptive(lw, seed, instance=0, eps=0.01, B_max=8192, anc=None,
+                                 B_used=None, ws=None, status=None, stream=None):
+    """Metropolis with B from eq. (5) for these weights, computed on the device."""
+    _need(lw, torch.float32, "lw")
+    P = lw.numel()
+    anc = torch.empty(P, dtype=torch.int32, device=lw.device) if anc is None else anc
+    _need(anc, torch.int32, "anc", P)
+    if B_used is not None:
+        _need(B_used, torch.int32, "B_used", 1)
+    if ws is None:
+        ws = workspace(P, _lib.METROPOLIS_ADAPTIVE, lw.device, stream)
+    check(lib.resample_metropolis_adaptive(_ptr(lw), _ptr(anc), P, float(eps), int(B_max),
+                                           int(seed), int(instance), _ptr(ws), ws.numel(),
+                                           _ptr(B_used), _status_ptr(status),
+                                           _stream_handle(stream)),
+          "resample_metropolis_adaptive")
+    return anc
+
+
 def _prefix(fn, kind, lw, seed, instance, anc, cumw, ws, status, stream):
     _need(lw, torch.float32, "lw")
     P = lw.numel()
@@ -192,3 +211,27 @@ RESAMPLERS = {
     "systematic": resample_systematic,
     "multinomial": resample_multinomial,
 }
+
+
+def filter_init(x, seed, stream=None):
+    """x[P, D] <- initial particles z(i, t = 0) (see include/resample.h)."""
+    _need(x, torch.float32, "x")
+    P, D = x.shape
+    check(lib.filter_init(_ptr(x), P, D, int(seed), _stream_handle(stream)), "filter_init")
+    return x
+
+
+def filter_propagate_weight(x_in, A, y_t, q, r, seed, t, x_out=None, lw=None, stream=None):
+    """One propagation + weighting step at time t >= 1; returns (x_out, lw)."""
+    _need(x_in, torch.float32, "x_in")
+    P, D = x_in.shape
+    x_out = torch.empty_like(x_in) if x_out is None else x_out
+    lw = torch.empty(P, dtype=torch.float32, device=x_in.device) if lw is None else lw
+    _need(x_out, torch.float32, "x_out", P * D)
+    _need(lw, torch.float32, "lw", P)
+    _need(A, torch.float64, "A", D * D)
+    _need(y_t, torch.float32, "y_t", D)
+    check(lib.filter_propagate_weight(_ptr(x_in), _ptr(x_out), _ptr(lw), P, D, _ptr(A), _ptr(y_t),
+                                      float(q), float(r), int(seed), int(t),
+                                      _stream_handle(stream)), "filter_propagate_weight")
+    return x_out, lw

@@ -1,0 +1,78 @@
+"""Batched resampling executor (binding of rs_batch_plan_init / resample_batch).
+
+A Batch holds a fixed set of instances (tensors for log-weights, ancestors and
+optionally state rows), the device plan and the workspace. run() enqueues the
+whole batch on the current stream and can be captured in a HIP graph; the
+plan itself is built by the native library.
+"""
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import check, lib
+from .api import METROPOLIS, STRATIFIED, SYSTEMATIC, _need, _stream_handle
+
+KINDS = {"metropolis": METROPOLIS, "stratified": STRATIFIED, "systematic": SYSTEMATIC}
+DEFAULT_TUNING = dict(chains_per_item=1024, unroll=8, lds_max_p=8192, blocks=0)
+
+
+class Batch:
+    def __init__(self, instances, tuning=None, device=None, stream=None, async_upload=False):
+        """instances: dicts with lw, anc, kind ('metropolis' | 'stratified' |
+        'systematic'), seed, instance, and optionally B, x_in, x_out, status.
+        With async_upload the plan goes through pinned host memory held by
+        this object and the call does not wait for the device."""
+        self.device = torch.device(device) if device is not None else torch.device(
+            "cuda", torch.cuda.current_device())
+        n = len(instances)
+        if n < 1:
+            raise ValueError("a batch needs at least one instance")
+        self.instances = list(instances)  # keeps the tensors alive
+        arr = (_lib.Instance * n)()
+        for k, d in enumerate(self.instances):
+            lw, anc = d["lw"], d["anc"]
+            _need(lw, torch.float32, "lw")
+            _need(anc, torch.int32, "anc", lw.numel())
+            x_in, x_out = d.get("x_in"), d.get("x_out")
+            D = 0
+            if x_in is not None:
+                _need(x_in, torch.float32, "x_in")
+                D = x_in.numel() // max(lw.numel(), 1)
+                _need(x_out, torch.float32, "x_out", x_in.numel())
+            st = d.get("status")
+            if st is not None:
+                _need(st, torch.int32, "status")
+            arr[k] = _lib.Instance(lw.data_ptr(), anc.data_ptr(),
+                                   x_in.data_ptr() if x_in is not None else None,
+                                   x_out.data_ptr() if x_out is not None else None,
+                                   st.data_ptr() if st is not None else None, lw.numel(), D,
+                                   KINDS[d["kind"]], int(d.get("B", 0)), int(d["instance"]),
+                                   int(d["seed"]))
+        self._arr = arr
+        t = dict(DEFAULT_TUNING, **(tuning or {}))
+        self.tuning = _lib.BatchTuning(t["chains_per_item"], t["unroll"], t["lds_max_p"],
+                                       t["blocks"])
+        pb = lib.rs_batch_plan_bytes(arr, n, ctypes.byref(self.tuning))
+        if pb == 0:
+            raise _lib.ResampleError("invalid batch instances or tuning")
+        wb = lib.rs_batch_workspace_bytes(arr, n)
+        self.plan_dev = torch.empty(pb, dtype=torch.uint8, device=self.device)
+        self.ws = torch.empty(max(wb, 256), dtype=torch.uint8, device=self.device)
+        self.plan = _lib.BatchPlan()
+        self.staging = (torch.empty(pb, dtype=torch.uint8, pin_memory=True) if async_upload
+                        else None)
+        check(lib.rs_batch_plan_init(ctypes.byref(self.plan), arr, n, ctypes.byref(self.tuning),
+                                     ctypes.c_void_p(self.plan_dev.data_ptr()), pb,
+                                     ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(),
+                                     ctypes.c_void_p(self.staging.data_ptr())
+                                     if self.staging is not None else None,
+                                     _stream_handle(stream)), "rs_batch_plan_init")
+
+    def run(self, stream=None):
+        check(lib.resample_batch(ctypes.byref(self.plan), _stream_handle(stream)),
+              "resample_batch")
+
+    @property
+    def particles(self):
+        return sum(d["lw"].numel() for d in self.instances)

@@ -1,0 +1,173 @@
+// Batched resampling: many independent instances of uneven size (a particle
+// MCMC run or a serving batch runs many filters at once; Sec. 1 of the paper
+// motivates the Metropolis resampler by exactly this repeated use) in one
+// graph replay of three persistent launches.
+//
+//   launch 1  tile reductions of every stratified/systematic instance
+//   launch 2  the per-instance tables (one block each)
+//   launch 3  Metropolis chains and stratified/systematic fills of every
+//             instance, each item followed by the ancestor-indexed copy of
+//             its rows (fused: the ancestors are still in LDS)
+//
+// Each launch is a persistent grid walking a static work list (items sorted
+// by decreasing cost, dealt out round-robin), so the grid never depends on
+// the data. Phases are ordered by kernel boundaries rather than by blocks
+// waiting on device-scope flags: on MI355X every cross-XCD publication needs
+// an L2 write-back, which costs far more than a launch boundary inside a
+// graph. Every item runs the same device bodies as the single-instance entry
+// points, so each instance's ancestors are bit-identical alone and in any
+// batch.
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+#include "launch.h"
+#include "metropolis_impl.h"
+#include "prefix.h"
+#include "prefix_impl.h"
+
+namespace rs {
+namespace {
+
+using namespace pfx;
+
+constexpr int kThreads = kTileThreads;  // every batched launch uses 256-thread blocks
+constexpr int64_t kTableLdsTiles = 4096;
+
+__global__ __launch_bounds__(kThreads) void batch_tile_kernel(const BatchInstance *insts,
+                                                              const int2 *items, int32_t n_items)
+{
+    for (int32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+        __syncthreads();  // LDS of the previous item is free
+        const int2 item = items[it];
+        const BatchInstance &I = insts[item.x];
+        tile_reduce_body(I.lw, I.P, item.y, I.ws);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void batch_table_kernel(const BatchInstance *insts,
+                                                               const int32_t *items,
+                                                               int32_t n_items, int use_lds)
+{
+    extern __shared__ double sh_tab[];
+    for (int32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+        __syncthreads();
+        const BatchInstance &I = insts[items[it]];
+        const WsView ws = ws_view(I.ws, I.P);
+        const int64_t n = num_tiles(I.P);
+        const bool lds = use_lds != 0;  // LDS sized for the largest table of the batch
+        double *bound = lds ? sh_tab : ws.bound;
+        int32_t *count = lds ? reinterpret_cast<int32_t *>(sh_tab + n) : ws.count;
+        if (I.kind == kStratified)
+            table_body<kStratified>(I.P, I.seed, I.instance, I.ws, I.status, nullptr, bound, count);
+        else
+            table_body<kSystematic>(I.P, I.seed, I.instance, I.ws, I.status, nullptr, bound, count);
+    }
+}
+
+// A Metropolis item: chains [first, first + count) of one instance, then the
+// copy of their rows. sh_anc holds the item's ancestors for the copy; w is
+// LDS-staged weights or the instance's lw.
+template <int UNROLL>
+__device__ void metropolis_item(const BatchInstance &I, int64_t first, int64_t count,
+                                float *staged, int32_t *sh_anc)
+{
+    const uint32_t P = (uint32_t)I.P;
+    const float *w = I.lw;
+    if (staged) {
+        for (uint32_t i = threadIdx.x; i < P; i += kThreads) staged[i] = I.lw[i];
+        __syncthreads();
+        w = staged;
+    }
+    int fl = 0;
+    for (int64_t r = threadIdx.x; r < count; r += kThreads) {
+        const uint32_t i = (uint32_t)(first + r);
+        fl |= mh::weight_flags(w[i]);
+        const int32_t a = (int32_t)mh::chain<UNROLL>(w, P, I.B, I.seed, I.instance, i);
+        I.anc[i] = a;
+        if (I.x_in) sh_anc[r] = a;
+    }
+    raise_flags(I.status, fl);
+    if (I.x_in) {
+        __syncthreads();
+        int cf = 0;
+        copy_rows_from_lds(sh_anc, first, first, first + count, I.x_in, I.x_out, I.D, I.P, &cf);
+        raise_flags(I.status, cf);
+    }
+}
+
+template <int UNROLL>
+__global__ __launch_bounds__(kThreads) void batch_main_kernel(const BatchInstance *insts,
+                                                              const int2 *items, int32_t n_items,
+                                                              int32_t chains_per_item,
+                                                              int64_t lds_max_p)
+{
+    extern __shared__ double sh_main[];  // [kChunk ints | union(kTile doubles, staged lw)]
+    int32_t *sh_anc = reinterpret_cast<int32_t *>(sh_main);
+    double *Cs = sh_main + kChunk / 2;
+    float *staging = reinterpret_cast<float *>(Cs);
+    for (int32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+        __syncthreads();
+        const int2 item = items[it];
+        const BatchInstance &I = insts[item.x];
+        if (I.kind == kMetropolisKind) {
+            const int64_t first = (int64_t)item.y * chains_per_item;
+            const int64_t count = min((int64_t)chains_per_item, I.P - first);
+            metropolis_item<UNROLL>(I, first, count, I.P <= lds_max_p ? staging : nullptr, sh_anc);
+        } else if (I.kind == kStratified) {
+            fill_body<kStratified>(I.lw, I.anc, I.P, I.seed, I.instance, nullptr, I.ws, item.y,
+                                   I.x_in, I.x_out, I.D, I.status, Cs, sh_anc);
+        } else {
+            fill_body<kSystematic>(I.lw, I.anc, I.P, I.seed, I.instance, nullptr, I.ws, item.y,
+                                   I.x_in, I.x_out, I.D, I.status, Cs, sh_anc);
+        }
+    }
+}
+
+uint32_t grid_of(int32_t items, int32_t blocks) { return (uint32_t)max(1, min(items, blocks)); }
+
+}  // namespace
+
+int launch_batch(const BatchLaunch &L, hipStream_t stream)
+{
+    if (L.n_tile_items > 0)
+        hipLaunchKernelGGL(batch_tile_kernel, dim3(grid_of(L.n_tile_items, L.blocks)),
+                           dim3(kThreads), 0, stream, L.insts, L.tile_items, L.n_tile_items);
+    if (L.n_table_items > 0) {
+        const int64_t n = L.max_table_tiles;
+        const int use_lds = n <= kTableLdsTiles ? 1 : 0;
+        const size_t smem = use_lds ? (size_t)n * (sizeof(double) + sizeof(int32_t)) : 0;
+        hipLaunchKernelGGL(batch_table_kernel, dim3(grid_of(L.n_table_items, L.blocks)),
+                           dim3(kThreads), smem, stream, L.insts, L.table_items, L.n_table_items,
+                           use_lds);
+    }
+    if (L.n_main_items > 0) {
+        const size_t smem = L.smem_main;
+        const dim3 grid(grid_of(L.n_main_items, L.blocks)), block(kThreads);
+#define RS_BATCH_CASE(U)                                                                         \
+    case U: {                                                                                    \
+        static size_t granted = 0;                                                               \
+        if (smem > granted) {                                                                    \
+            if (hipFuncSetAttribute(reinterpret_cast<const void *>(&batch_main_kernel<U>),       \
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,                  \
+                                    (int)smem) != hipSuccess)                                    \
+                return launch_status();                                                          \
+            granted = smem;                                                                      \
+        }                                                                                        \
+        hipLaunchKernelGGL(batch_main_kernel<U>, grid, block, smem, stream, L.insts, L.main_items, \
+                           L.n_main_items, L.chains_per_item, L.lds_max_p);                      \
+        break;                                                                                   \
+    }
+        switch (L.unroll) {
+            RS_BATCH_CASE(2)
+            RS_BATCH_CASE(4)
+            RS_BATCH_CASE(8)
+            RS_BATCH_CASE(16)
+        default:
+            return -1;
+        }
+#undef RS_BATCH_CASE
+    }
+    return launch_status();
+}
+
+}  // namespace rs

@@ -7,9 +7,24 @@
 #include <cstdlib>
 #include <mutex>
 
+#include "analysis.h"
 #include "launch.h"
 #include "prefix.h"
 #include "resample.h"
+
+namespace {
+thread_local hipError_t g_last_hip_error = hipSuccess;
+}  // namespace
+
+namespace rs {
+int record_hip_error(hipError_t e)
+{
+    if (e == hipSuccess) return 0;
+    g_last_hip_error = e;
+    return -3;
+}
+int launch_status() { return record_hip_error(hipGetLastError()); }
+}  // namespace rs
 
 namespace {
 
@@ -94,13 +109,16 @@ const char *rs_strerror(int code)
 
 int rs_version(void) { return 100; }
 
+const char *rs_last_hip_error(void) { return hipGetErrorString(g_last_hip_error); }
+
 size_t rs_workspace_bytes(int64_t P, int resampler)
 {
     if (P < 1) return 0;
     switch (resampler) {
     case RS_STRATIFIED:
     case RS_SYSTEMATIC:
-    case RS_LOG_SUM_EXP: return rs::ws_layout(P, false).total;
+    case RS_LOG_SUM_EXP:
+    case RS_METROPOLIS_ADAPTIVE: return rs::ws_layout(P, false).total;
     case RS_MULTINOMIAL: return rs::ws_layout(P, true).total;
     default: return 0;
     }
@@ -177,19 +195,45 @@ int rs_log_sum_exp(const float *lw, int64_t P, double *out, void *ws, size_t ws_
 
 uint32_t metropolis_B(int64_t P, double w_max, double eps)
 {
-    // Eq. (4): lambda^B <= eps (alpha + beta) / max(alpha, beta); eq. (5)
-    // solves it for 0 < lambda < 1. lambda = 0 (uniform weights) needs one step.
-    if (P < 2 || !(w_max > 0.0) || w_max > 1.0 || !(eps > 0.0)) return 0;
-    const double beta = 1.0 / (double)P;
-    const double alpha = (1.0 - w_max) / ((double)P * w_max);
-    const double lambda = 1.0 - alpha - beta;
-    const double rhs = eps * (alpha + beta) / std::fmax(alpha, beta);
-    if (rhs >= 1.0) return 0;
-    if (!(lambda > 0.0)) return 1;
-    const double b = std::ceil(std::log(rhs) / std::log(lambda));
-    if (!(b > 0.0)) return 0;
-    if (b >= 4294967295.0) return 4294967295u;
-    return (uint32_t)b;
+    return rs::iterations_for(P, w_max, eps);
+}
+
+int resample_metropolis_adaptive(const float *lw, int32_t *anc, int64_t P, double eps,
+                                 uint32_t B_max, uint64_t seed, uint32_t instance, void *ws,
+                                 size_t ws_bytes, uint32_t *B_used, int32_t *status,
+                                 hipStream_t stream)
+{
+    if (P == 0) return RS_OK;
+    if (!lw || !anc || !ws || P < 0 || P > kMaxP || !(eps > 0.0)) return RS_EINVAL;
+    if (overlaps(lw, 4 * (size_t)P, anc, 4 * (size_t)P)) return RS_EINVAL;
+    if (ws_bytes < rs_workspace_bytes(P, RS_METROPOLIS_ADAPTIVE)) return RS_EWORKSPACE;
+    if (overlaps(ws, ws_bytes, lw, 4 * (size_t)P) || overlaps(ws, ws_bytes, anc, 4 * (size_t)P))
+        return RS_EINVAL;
+    const rs::MetropolisTuning t = current_tuning();
+    return map_rc(rs::launch_metropolis_adaptive(lw, anc, P, eps, B_max, seed, instance, ws,
+                                                 B_used, status, t, stream));
+}
+
+int filter_init(float *x, int64_t P, int32_t D, uint64_t seed, hipStream_t stream)
+{
+    if (P == 0) return RS_OK;
+    if (!x || P < 0 || P > kMaxP || D < 1 || D > 64) return RS_EINVAL;
+    return map_rc(rs::launch_filter_init(x, P, D, seed, stream));
+}
+
+int filter_propagate_weight(const float *x_in, float *x_out, float *lw, int64_t P, int32_t D,
+                            const double *A, const float *y, double q, double r, uint64_t seed,
+                            uint32_t t, hipStream_t stream)
+{
+    if (P == 0) return RS_OK;
+    if (!x_in || !x_out || !lw || !A || !y || P < 0 || P > kMaxP || D < 1 || D > 64)
+        return RS_EINVAL;
+    if (!(q >= 0.0) || !(r > 0.0)) return RS_EINVAL;
+    const size_t rows = (size_t)P * (size_t)D * sizeof(float);
+    if (overlaps(x_in, rows, x_out, rows) || overlaps(lw, 4 * (size_t)P, x_out, rows) ||
+        overlaps(lw, 4 * (size_t)P, x_in, rows))
+        return RS_EINVAL;
+    return map_rc(rs::launch_filter_step(x_in, x_out, lw, P, D, A, y, q, r, seed, t, stream));
 }
 
 int rs_log_u_table(float *approx, float *exact, hipStream_t stream)

@@ -1,0 +1,146 @@
+// Bootstrap particle filter steps around the resampler (Sec. 1 of the paper:
+// initialisation, propagation, weighting; resampling is the library's other
+// entry points). Model: x_0 ~ N(0, I), x_t = A x_{t-1} + N(0, q I),
+// y_t = x_t + N(0, r I). The proposal is the transition, so the log-weight is
+// the observation log-density.
+//
+// Gaussian noise: Box-Muller on Philox block (i, t, h, 5) for components
+// 4h .. 4h+3: words (r0, r1) give components 4h, 4h+1 and (r2, r3) give
+// 4h+2, 4h+3, with u1 = (r + 1/2) 2^-32, u2 = r' 2^-32,
+// z = sqrt(-2 log u1) (cos, sin)(2 pi u2). Time 0 draws the initial state.
+//
+// One thread per particle; the D x D transition matrix sits in LDS; the
+// matrix-vector product and the weight accumulate in binary64 and round to
+// binary32 state once per component. Rows are read and written as 16-byte
+// vectors when D is a multiple of 4.
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+#include "launch.h"
+
+namespace rs {
+namespace {
+
+constexpr int kFilterThreads = 256;
+constexpr int kMaxD = 64;
+
+__device__ __forceinline__ void normals(uint64_t seed, uint32_t i, uint32_t t, int D, double *z)
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int h = 0; 4 * h < D; ++h) {
+        const Block4 b = philox(seed, i, t, (uint32_t)h, kTagFilterNoise);
+        const uint32_t r[4] = {b.r0, b.r1, b.r2, b.r3};
+#pragma unroll
+        for (int pair = 0; pair < 2; ++pair) {
+            const double u1 = ((double)r[2 * pair] + 0.5) * 0x1p-32;
+            const double u2 = (double)r[2 * pair + 1] * 0x1p-32;
+            const double rad = sqrt(-2.0 * log(u1));
+            const int d0 = 4 * h + 2 * pair;
+            if (d0 < D) z[d0] = rad * cos(two_pi * u2);
+            if (d0 + 1 < D) z[d0 + 1] = rad * sin(two_pi * u2);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kFilterThreads) void filter_init_kernel(float *__restrict__ x,
+                                                                     int64_t P, int D,
+                                                                     uint64_t seed)
+{
+    double z[kMaxD];
+    for (int64_t i = blockIdx.x * (int64_t)kFilterThreads + threadIdx.x; i < P;
+         i += (int64_t)gridDim.x * kFilterThreads) {
+        normals(seed, (uint32_t)i, 0u, D, z);
+        for (int d = 0; d < D; ++d) x[i * D + d] = (float)z[d];
+    }
+}
+
+template <int DC>  // compile-time D (0 = runtime D)
+__global__ __launch_bounds__(kFilterThreads) void propagate_weight_kernel(
+    const float *__restrict__ x_in, float *__restrict__ x_out, float *__restrict__ lw, int64_t P,
+    int Drt, const double *__restrict__ A, const float *__restrict__ y, double sq, double r,
+    double norm, uint64_t seed, uint32_t t)
+{
+    const int D = DC > 0 ? DC : Drt;
+    __shared__ double sA[kMaxD * kMaxD];
+    __shared__ double sy[kMaxD];
+    for (int k = threadIdx.x; k < D * D; k += kFilterThreads) sA[k] = A[k];
+    for (int k = threadIdx.x; k < D; k += kFilterThreads) sy[k] = (double)y[k];
+    __syncthreads();
+    double z[DC > 0 ? DC : kMaxD];
+    double xv[DC > 0 ? DC : kMaxD];
+    for (int64_t i = blockIdx.x * (int64_t)kFilterThreads + threadIdx.x; i < P;
+         i += (int64_t)gridDim.x * kFilterThreads) {
+        const float *xi = x_in + i * D;
+        if (DC > 0 && DC % 4 == 0) {
+#pragma unroll
+            for (int q = 0; q < D / 4; ++q) {
+                const float4 v = reinterpret_cast<const float4 *>(xi)[q];
+                xv[4 * q] = v.x; xv[4 * q + 1] = v.y; xv[4 * q + 2] = v.z; xv[4 * q + 3] = v.w;
+            }
+        } else {
+            for (int d = 0; d < D; ++d) xv[d] = (double)xi[d];
+        }
+        normals(seed, (uint32_t)i, t, D, z);
+        double ss = 0.0;
+        float out[DC > 0 ? DC : kMaxD];
+        for (int a = 0; a < D; ++a) {
+            double acc = 0.0;
+            for (int b = 0; b < D; ++b) acc += sA[a * D + b] * xv[b];
+            const float xa = (float)(acc + sq * z[a]);
+            out[a] = xa;
+            const double e = sy[a] - (double)xa;
+            ss += e * e;
+        }
+        float *xo = x_out + i * D;
+        if (DC > 0 && DC % 4 == 0) {
+#pragma unroll
+            for (int q = 0; q < D / 4; ++q)
+                reinterpret_cast<float4 *>(xo)[q] =
+                    make_float4(out[4 * q], out[4 * q + 1], out[4 * q + 2], out[4 * q + 3]);
+        } else {
+            for (int d = 0; d < D; ++d) xo[d] = out[d];
+        }
+        lw[i] = (float)(norm - 0.5 * ss / r);
+    }
+}
+
+uint32_t filter_grid(int64_t P)
+{
+    int64_t g = (P + kFilterThreads - 1) / kFilterThreads;
+    if (g < 1) g = 1;
+    if (g > 65535) g = 65535;
+    return (uint32_t)g;
+}
+
+}  // namespace
+
+int launch_filter_init(float *x, int64_t P, int32_t D, uint64_t seed, hipStream_t stream)
+{
+    hipLaunchKernelGGL(filter_init_kernel, dim3(filter_grid(P)), dim3(kFilterThreads), 0, stream,
+                       x, P, (int)D, seed);
+    return launch_status();
+}
+
+int launch_filter_step(const float *x_in, float *x_out, float *lw, int64_t P, int32_t D,
+                       const double *A, const float *y, double q, double r, uint64_t seed,
+                       uint32_t t, hipStream_t stream)
+{
+    const double log_two_pi = 1.8378770664093454835606594728112;
+    const double norm = -0.5 * (double)D * (log_two_pi + log(r));
+    const double sq = sqrt(q);
+    const bool vec = ((((uintptr_t)x_in) | ((uintptr_t)x_out)) & 15) == 0;
+    const dim3 grid(filter_grid(P)), block(kFilterThreads);
+    if (D == 8 && vec) {
+        hipLaunchKernelGGL(propagate_weight_kernel<8>, grid, block, 0, stream, x_in, x_out, lw, P,
+                           (int)D, A, y, sq, r, norm, seed, t);
+    } else if (D == 4 && vec) {
+        hipLaunchKernelGGL(propagate_weight_kernel<4>, grid, block, 0, stream, x_in, x_out, lw, P,
+                           (int)D, A, y, sq, r, norm, seed, t);
+    } else {
+        hipLaunchKernelGGL(propagate_weight_kernel<0>, grid, block, 0, stream, x_in, x_out, lw, P,
+                           (int)D, A, y, sq, r, norm, seed, t);
+    }
+    return launch_status();
+}
+
+}  // namespace rs

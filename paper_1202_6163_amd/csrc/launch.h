@@ -8,6 +8,11 @@
 
 namespace rs {
 
+// 0 if no HIP error is pending, else -3 after recording the error for
+// rs_last_hip_error().
+int launch_status();
+int record_hip_error(hipError_t e);
+
 struct MetropolisTuning {
     int32_t block;
     int32_t unroll;
@@ -21,12 +26,29 @@ int launch_metropolis(const float *lw, int32_t *anc, int64_t P, uint32_t B, uint
 
 int launch_log_u_table(float *approx, float *exact, hipStream_t stream);
 
+// Metropolis with B read from device memory (B_dev, capped by B) after the
+// launches before it on the stream computed it.
+int launch_metropolis_dev_B(const float *lw, int32_t *anc, int64_t P, uint32_t B,
+                            const uint32_t *B_dev, uint64_t seed, uint32_t instance,
+                            int32_t *status, const MetropolisTuning &tune, hipStream_t stream);
+
+int launch_metropolis_adaptive(const float *lw, int32_t *anc, int64_t P, double eps,
+                               uint32_t B_max, uint64_t seed, uint32_t instance, void *ws,
+                               uint32_t *B_used, int32_t *status, const MetropolisTuning &tune,
+                               hipStream_t stream);
+
 int launch_prefix(int kind, const float *lw, int32_t *anc, int64_t P, uint64_t seed,
                   uint32_t instance, double *cumw, void *ws, int32_t *status,
                   hipStream_t stream);
 
 int launch_log_sum_exp(const float *lw, int64_t P, double *out, void *ws, int32_t *status,
                        hipStream_t stream);
+
+// Tile reduction + table that leaves the eq. (5) iteration count (capped by
+// B_max) in the workspace header (adaptive_B_slot) and in *B_used if given.
+int launch_adaptive_B(const float *lw, int64_t P, double eps, uint32_t B_max, void *ws,
+                      uint32_t *B_used, int32_t *status, hipStream_t stream);
+const uint32_t *adaptive_B_slot(const void *ws);
 
 int launch_offspring(const int32_t *anc, int32_t *off, int64_t P, int32_t *status,
                      hipStream_t stream);
@@ -35,5 +57,43 @@ int launch_permute_copy(const int32_t *anc, const float *x_in, float *x_out, int
                         int32_t *status, hipStream_t stream);
 
 int launch_zero(void *ptr, size_t bytes, hipStream_t stream);
+
+// ---------------------------------------------------------------- batches
+constexpr int kMetropolisKind = 3;  // RS_METROPOLIS
+
+// One instance of a batch as the kernels read it (device memory).
+struct BatchInstance {
+    const float *lw;
+    int32_t *anc;
+    const float *x_in;  // nullptr: no copy
+    float *x_out;
+    int32_t *status;
+    char *ws;           // this instance's prefix workspace (stratified/systematic)
+    int64_t P;
+    uint64_t seed;
+    uint32_t B;
+    uint32_t instance;
+    int32_t D;
+    int32_t kind;
+};
+
+struct BatchLaunch {
+    const BatchInstance *insts;
+    const int2 *tile_items;     // (instance, tile)
+    const int32_t *table_items; // instance
+    const int2 *main_items;     // (instance, fill block or Metropolis item)
+    int32_t n_tile_items, n_table_items, n_main_items;
+    int32_t blocks, unroll, chains_per_item;
+    int64_t lds_max_p, max_table_tiles;
+    size_t smem_main;
+};
+
+int launch_batch(const BatchLaunch &launch, hipStream_t stream);
+
+int launch_filter_init(float *x, int64_t P, int32_t D, uint64_t seed, hipStream_t stream);
+
+int launch_filter_step(const float *x_in, float *x_out, float *lw, int64_t P, int32_t D,
+                       const double *A, const float *y, double q, double r, uint64_t seed,
+                       uint32_t t, hipStream_t stream);
 
 }  // namespace rs

@@ -29,36 +29,22 @@
 
 #include "common.h"
 #include "launch.h"
+#include "metropolis_impl.h"
 
 namespace rs {
 namespace {
 
-constexpr float kLn2 = 0.693147180559945309417f;
-constexpr float kFastMargin = 0x1p-16f;
-
-__device__ __forceinline__ float approx_log_u(float u)
-{
-    return __builtin_amdgcn_logf(u) * kLn2;
-}
-
-// Exact decision of L(u) < d, L the correctly rounded binary32 log.
-__device__ __forceinline__ bool accept_move(float d, float la, float u)
-{
-    if (!(d < 0.0f)) return d >= 0.0f;
-    const float t = fabsf(la) * kFastMargin;
-    if (la + t < d) return true;
-    if (la - t >= d) return false;
-    return exact_log_u(u) < d;
-}
+using namespace mh;
 
 template <int UNROLL, bool STAGE>
 __global__ __launch_bounds__(1024) void metropolis_kernel(const float *__restrict__ lw,
                                                           int32_t *__restrict__ anc, uint32_t P,
                                                           uint32_t B, uint64_t seed,
                                                           uint32_t instance, int lpc_log2,
-                                                          int32_t *status)
+                                                          int32_t *status, const uint32_t *B_dev)
 {
     static_assert(UNROLL % 2 == 0, "one Philox block feeds two iterations");
+    if (B_dev) B = min(B, *B_dev);  // iteration count computed on the device
     extern __shared__ float staged[];
     const float *w = lw;
     if (STAGE) {
@@ -77,53 +63,31 @@ __global__ __launch_bounds__(1024) void metropolis_kernel(const float *__restric
     for (uint64_t gt = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; gt < total; gt += stride) {
         const uint32_t i = (uint32_t)(gt >> lpc_log2);
         const uint32_t g = (uint32_t)(gt & (G - 1));
+        if (g == 0) raise_flags(status, weight_flags(w[i]));
+        if (G == 1) {
+            anc[i] = (int32_t)chain<UNROLL>(w, P, B, seed, instance, i);
+            continue;
+        }
         uint32_t k = i;
         float lk = w[i];
-        if (g == 0) {
-            int fl = 0;
-            if (isnan(lk)) fl |= kFlagNan;
-            else if (isinf(lk) && lk > 0.0f) fl |= kFlagPosInf;
-            raise_flags(status, fl);
-        }
         for (uint32_t r0 = 0; r0 < B; r0 += G * UNROLL) {
             const uint32_t n0 = r0 + g * UNROLL;  // even
             uint32_t jj[UNROLL];
             float uu[UNROLL], vv[UNROLL], la[UNROLL];
+            draw_round<UNROLL>(w, P, seed, instance, i, n0, jj, vv, uu, la);
+            // decisions in iteration order: lane gg of the group, then the next
+            for (uint32_t gg = 0; gg < G; ++gg) {
+                if (g == gg) {
 #pragma unroll
-            for (int p = 0; p < UNROLL / 2; ++p) {
-                const Block4 b = philox(seed, i, instance, (n0 >> 1) + (uint32_t)p, kTagMetropolis);
-                jj[2 * p] = uniform_index(b.r0, P);
-                uu[2 * p] = grid_uniform(b.r1);
-                jj[2 * p + 1] = uniform_index(b.r2, P);
-                uu[2 * p + 1] = grid_uniform(b.r3);
-            }
-#pragma unroll
-            for (int s = 0; s < UNROLL; ++s) {
-                vv[s] = w[jj[s]];
-                la[s] = approx_log_u(uu[s]);
-            }
-            if (G == 1) {
-#pragma unroll
-                for (int s = 0; s < UNROLL; ++s) {
-                    if (n0 + s < B && accept_move(vv[s] - lk, la[s], uu[s])) {
-                        k = jj[s];
-                        lk = vv[s];
-                    }
-                }
-            } else {
-                for (uint32_t gg = 0; gg < G; ++gg) {
-                    if (g == gg) {
-#pragma unroll
-                        for (int s = 0; s < UNROLL; ++s) {
-                            if (n0 + s < B && accept_move(vv[s] - lk, la[s], uu[s])) {
-                                k = jj[s];
-                                lk = vv[s];
-                            }
+                    for (int s = 0; s < UNROLL; ++s) {
+                        if (n0 + s < B && accept_move(vv[s] - lk, la[s], uu[s])) {
+                            k = jj[s];
+                            lk = vv[s];
                         }
                     }
-                    k = (uint32_t)__shfl((int)k, src_base + (int)gg, kWave);
-                    lk = __shfl(lk, src_base + (int)gg, kWave);
                 }
+                k = (uint32_t)__shfl((int)k, src_base + (int)gg, kWave);
+                lk = __shfl(lk, src_base + (int)gg, kWave);
             }
         }
         if (g == 0) anc[i] = (int32_t)k;
@@ -133,7 +97,7 @@ __global__ __launch_bounds__(1024) void metropolis_kernel(const float *__restric
 template <int UNROLL, bool STAGE>
 int launch_variant(const float *lw, int32_t *anc, uint32_t P, uint32_t B, uint64_t seed,
                    uint32_t instance, int lpc_log2, int block, int32_t *status,
-                   hipStream_t stream)
+                   const uint32_t *B_dev, hipStream_t stream)
 {
     const uint64_t threads = (uint64_t)P << lpc_log2;
     uint64_t grid = (threads + block - 1) / block;
@@ -141,19 +105,18 @@ int launch_variant(const float *lw, int32_t *anc, uint32_t P, uint32_t B, uint64
     size_t smem = 0;
     if (STAGE) {
         smem = (size_t)P * sizeof(float);
-        static bool attr_set = false;
-        if (!attr_set) {
-            int dev = 0, max_smem = 0;
-            (void)hipGetDevice(&dev);
-            (void)hipDeviceGetAttribute(&max_smem, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-            (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&metropolis_kernel<UNROLL, STAGE>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, max_smem);
-            attr_set = true;
+        static size_t granted = 0;  // dynamic LDS granted to this kernel so far
+        if (smem > granted) {
+            if (hipFuncSetAttribute(reinterpret_cast<const void *>(&metropolis_kernel<UNROLL, STAGE>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)smem) != hipSuccess)
+                return launch_status();
+            granted = smem;
         }
     }
     hipLaunchKernelGGL((metropolis_kernel<UNROLL, STAGE>), dim3((uint32_t)grid), dim3(block),
-                       smem, stream, lw, anc, P, B, seed, instance, lpc_log2, status);
-    return hipGetLastError() == hipSuccess ? 0 : -3;
+                       smem, stream, lw, anc, P, B, seed, instance, lpc_log2, status, B_dev);
+    return launch_status();
 }
 
 // Lanes per chain when not fixed by the tuning: enough lanes to fill the
@@ -183,12 +146,12 @@ int launch_log_u_table(float *approx, float *exact, hipStream_t stream)
 {
     hipLaunchKernelGGL(log_u_table_kernel, dim3((1u << 23) / 256), dim3(256), 0, stream, approx,
                        exact);
-    return hipGetLastError() == hipSuccess ? 0 : -3;
+    return launch_status();
 }
 
-int launch_metropolis(const float *lw, int32_t *anc, int64_t P, uint32_t B, uint64_t seed,
-                      uint32_t instance, int32_t *status, const MetropolisTuning &tune,
-                      hipStream_t stream)
+int launch_metropolis_dev_B(const float *lw, int32_t *anc, int64_t P, uint32_t B,
+                            const uint32_t *B_dev, uint64_t seed, uint32_t instance,
+                            int32_t *status, const MetropolisTuning &tune, hipStream_t stream)
 {
     const uint32_t p = (uint32_t)P;
     int lg = 0;
@@ -205,9 +168,9 @@ int launch_metropolis(const float *lw, int32_t *anc, int64_t P, uint32_t B, uint
 #define RS_METRO_CASE(U)                                                                       \
     case U:                                                                                    \
         return stage ? launch_variant<U, true>(lw, anc, p, B, seed, instance, lg, blk, status, \
-                                               stream)                                         \
+                                               B_dev, stream)                                  \
                      : launch_variant<U, false>(lw, anc, p, B, seed, instance, lg, blk,        \
-                                                status, stream);
+                                                status, B_dev, stream);
     switch (tune.unroll) {
         RS_METRO_CASE(2)
         RS_METRO_CASE(4)
@@ -217,6 +180,24 @@ int launch_metropolis(const float *lw, int32_t *anc, int64_t P, uint32_t B, uint
         return -1;
     }
 #undef RS_METRO_CASE
+}
+
+int launch_metropolis(const float *lw, int32_t *anc, int64_t P, uint32_t B, uint64_t seed,
+                      uint32_t instance, int32_t *status, const MetropolisTuning &tune,
+                      hipStream_t stream)
+{
+    return launch_metropolis_dev_B(lw, anc, P, B, nullptr, seed, instance, status, tune, stream);
+}
+
+int launch_metropolis_adaptive(const float *lw, int32_t *anc, int64_t P, double eps,
+                               uint32_t B_max, uint64_t seed, uint32_t instance, void *ws,
+                               uint32_t *B_used, int32_t *status, const MetropolisTuning &tune,
+                               hipStream_t stream)
+{
+    const int rc = launch_adaptive_B(lw, P, eps, B_max, ws, B_used, status, stream);
+    if (rc) return rc;
+    return launch_metropolis_dev_B(lw, anc, P, B_max, adaptive_B_slot(ws), seed, instance, status,
+                                   tune, stream);
 }
 
 }  // namespace rs

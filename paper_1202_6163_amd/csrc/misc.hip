@@ -153,7 +153,7 @@ int launch_zero(void *ptr, size_t bytes, hipStream_t stream)
     if (bytes == 0) return 0;
     hipLaunchKernelGGL(zero_kernel, dim3(grid_for((int64_t)(bytes / 16 + 1))), dim3(kThreads), 0,
                        stream, static_cast<uint8_t *>(ptr), bytes);
-    return hipGetLastError() == hipSuccess ? 0 : -3;
+    return launch_status();
 }
 
 int launch_offspring(const int32_t *anc, int32_t *off, int64_t P, int32_t *status,
@@ -163,7 +163,7 @@ int launch_offspring(const int32_t *anc, int32_t *off, int64_t P, int32_t *statu
     if (rc) return rc;
     hipLaunchKernelGGL(offspring_kernel, dim3(grid_for(P)), dim3(kThreads), 0, stream, anc, off, P,
                        status);
-    return hipGetLastError() == hipSuccess ? 0 : -3;
+    return launch_status();
 }
 
 int launch_permute_copy(const int32_t *anc, const float *x_in, float *x_out, int64_t P, int32_t D,
@@ -187,7 +187,7 @@ int launch_permute_copy(const int32_t *anc, const float *x_in, float *x_out, int
         hipLaunchKernelGGL(copy_rows_scalar, dim3(grid_for(P * (int64_t)D)), dim3(kThreads), 0,
                            stream, anc, x_in, x_out, P, D, status);
     }
-    return hipGetLastError() == hipSuccess ? 0 : -3;
+    return launch_status();
 }
 
 }  // namespace rs

@@ -19,7 +19,6 @@ namespace rs {
 
 constexpr int kTile = 1024;          // weights per tile
 constexpr int kTileThreads = 256;    // threads per tile block (4 weights each)
-constexpr int kTableThreads = 1024;  // threads of the single table block
 constexpr int kChunk = 2048;         // outputs per fill block (8 per thread)
 
 // Kinds of prefix-sum pass.
@@ -27,6 +26,7 @@ constexpr int kStratified = 0;
 constexpr int kSystematic = 1;
 constexpr int kMultinomial = 2;
 constexpr int kLogSumExp = 4;
+constexpr int kAdaptiveB = 5;  // log-sum-exp plus the eq. (5) iteration count
 
 struct alignas(64) WsHeader {
     int flags;       // OR of data flags; nonzero = table invalid
@@ -36,6 +36,8 @@ struct alignas(64) WsHeader {
     double W;        // total weight sum exp(lw - m)
     double delta;    // W / P
     double lse;      // m + log W
+    uint32_t B;      // adaptive Metropolis iterations (eq. (5) at w_max = 1 / W)
+    uint32_t pad2;
 };
 
 struct WsLayout {

@@ -1,0 +1,552 @@
+// Device bodies of the prefix-sum resamplers, shared by the single-call
+// kernels (prefix.hip) and the batched persistent kernels (batch.hip) so that
+// a resampling instance computes exactly the same values on either path.
+// See prefix.hip for the method and the design.
+//
+// Every body is executed by all kTileThreads threads of a block; decisions
+// that lead to a barrier are uniform across the block.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "analysis.h"
+#include "common.h"
+#include "prefix.h"
+
+namespace rs {
+namespace pfx {
+
+constexpr int kNW = kTileThreads / kWave;  // waves per block
+
+// ---------------------------------------------------------------- block ops
+__device__ inline double block_sum(double v, double *red)
+{
+    v = wave_sum(v);
+    if (lane_id() == 0) red[wave_id()] = v;
+    __syncthreads();
+    double s = red[0];
+    for (int w = 1; w < kNW; ++w) s += red[w];
+    __syncthreads();
+    return s;
+}
+
+__device__ inline float block_max(float v, float *red)
+{
+    v = wave_max(v);
+    if (lane_id() == 0) red[wave_id()] = v;
+    __syncthreads();
+    float s = red[0];
+    for (int w = 1; w < kNW; ++w) s = fmaxf(s, red[w]);
+    __syncthreads();
+    return s;
+}
+
+__device__ inline int block_or(int v, int *red)
+{
+    v = wave_or(v);
+    if (lane_id() == 0) red[wave_id()] = v;
+    __syncthreads();
+    int s = 0;
+    for (int w = 0; w < kNW; ++w) s |= red[w];
+    __syncthreads();
+    return s;
+}
+
+// Exclusive prefix sum over threads.
+__device__ inline double block_exclusive_sum(double v, double *red)
+{
+    const int lane = lane_id(), wave = wave_id();
+    const double incl = wave_inclusive_sum(v);
+    double excl = __shfl_up(incl, 1, kWave);
+    if (lane == 0) excl = 0.0;
+    if (lane == kWave - 1) red[wave] = incl;
+    __syncthreads();
+    double wp = 0.0;
+    for (int w = 0; w < wave; ++w) wp += red[w];
+    __syncthreads();
+    return wp + excl;
+}
+
+// Exclusive prefix maximum over threads of non-negative values (0 first).
+__device__ inline double block_exclusive_max(double v, double *red)
+{
+    const int lane = lane_id(), wave = wave_id();
+    double incl = v;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const double y = __shfl_up(incl, off, kWave);
+        if (lane >= off) incl = fmax(incl, y);
+    }
+    double excl = __shfl_up(incl, 1, kWave);
+    if (lane == 0) excl = 0.0;
+    if (lane == kWave - 1) red[wave] = incl;
+    __syncthreads();
+    double wp = 0.0;
+    for (int w = 0; w < wave; ++w) wp = fmax(wp, red[w]);
+    __syncthreads();
+    return fmax(wp, excl);
+}
+
+__device__ inline int64_t block_exclusive_isum(int64_t v, int64_t *red, int64_t *total)
+{
+    const int lane = lane_id(), wave = wave_id();
+    int64_t incl = v;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int64_t y = __shfl_up(incl, off, kWave);
+        if (lane >= off) incl += y;
+    }
+    int64_t excl = __shfl_up(incl, 1, kWave);
+    if (lane == 0) excl = 0;
+    if (lane == kWave - 1) red[wave] = incl;
+    __syncthreads();
+    int64_t wp = 0, tot = 0;
+    for (int w = 0; w < kNW; ++w) {
+        if (w < wave) wp += red[w];
+        tot += red[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return wp + excl;
+}
+
+// The four consecutive log-weights of this thread in tile t (-inf past P).
+__device__ __forceinline__ void load_tile4(const float *__restrict__ lw, int64_t P, int64_t t,
+                                           float v[4])
+{
+    const int64_t base = t * kTile + 4 * (int64_t)threadIdx.x;
+    const bool aligned = (((uintptr_t)lw) & 15) == 0;
+    if (aligned && base + 3 < P) {
+        const float4 q = *reinterpret_cast<const float4 *>(lw + base);
+        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = (base + k < P) ? lw[base + k] : -INFINITY;
+    }
+}
+
+struct WsView {
+    WsHeader *h;
+    float *tile_max;
+    double *tile_sum;
+    int32_t *tile_flags;
+    double *bound;
+    int32_t *count;
+    int32_t *overflow;
+};
+
+__device__ __forceinline__ WsView ws_view(char *ws, int64_t P)
+{
+    const WsLayout L = ws_layout(P, false);
+    WsView v;
+    v.h = reinterpret_cast<WsHeader *>(ws + L.header);
+    v.tile_max = reinterpret_cast<float *>(ws + L.tile_max);
+    v.tile_sum = reinterpret_cast<double *>(ws + L.tile_sum);
+    v.tile_flags = reinterpret_cast<int32_t *>(ws + L.tile_flags);
+    v.bound = reinterpret_cast<double *>(ws + L.bound);
+    v.count = reinterpret_cast<int32_t *>(ws + L.count);
+    v.overflow = reinterpret_cast<int32_t *>(ws + L.overflow);
+    return v;
+}
+
+// ------------------------------------------------------ draw points
+template <int KIND>
+__device__ __forceinline__ double draw_point(int64_t i, double delta, uint64_t seed,
+                                             uint32_t instance, double u_sys)
+{
+    if (KIND == kStratified) {
+        const Block4 b = philox(seed, (uint32_t)(i >> 2), instance, 0u, kTagStratified);
+        return ((double)i + unit32(word(b, (uint32_t)(i & 3)))) * delta;
+    }
+    return ((double)i + u_sys) * delta;
+}
+
+__device__ __forceinline__ double systematic_offset(uint64_t seed, uint32_t instance)
+{
+    return unit32(philox(seed, 0u, instance, 0u, kTagSystematic).r0);
+}
+
+// N(c) = #{i : x_i < c} for the non-decreasing stratified/systematic draw
+// points, or P when c >= W (draws at or past W belong to the last positive
+// tile). With e = floor(c / (W/P)), x_{e-2} < c <= x_{e+2} up to rounding, so
+// the five draws e-2 .. e+2 (two Philox blocks) settle the answer; a
+// bisection over all P covers anything else.
+template <int KIND>
+__device__ int64_t count_below(double c, int64_t P, double W, double delta, uint64_t seed,
+                               uint32_t instance, double u_sys)
+{
+    if (c >= W) return P;
+    if (!(c > 0.0)) return 0;
+    const double est = floor(c / delta);
+    const int64_t e = est > (double)P ? P : (int64_t)est;
+    const int64_t s = e >= 2 ? e - 2 : 0;  // window s .. s+4
+    double x[5];
+    if (KIND == kStratified) {
+        const Block4 b0 = philox(seed, (uint32_t)(s >> 2), instance, 0u, kTagStratified);
+        const Block4 b1 = philox(seed, (uint32_t)(s >> 2) + 1u, instance, 0u, kTagStratified);
+        const uint32_t r[8] = {b0.r0, b0.r1, b0.r2, b0.r3, b1.r0, b1.r1, b1.r2, b1.r3};
+        const int off = (int)(s & 3);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) x[k] = ((double)(s + k) + unit32(r[off + k])) * delta;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) x[k] = ((double)(s + k) + u_sys) * delta;
+    }
+    // valid when every draw before the window is below c: s = 0 or x_s < c
+    if (s == 0 || x[0] < c) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            if (s + k >= P) return P;
+            if (x[k] >= c) return s + k;
+        }
+    }
+    int64_t lo = 0, hi = P;  // fallback (not expected): bisection
+    while (lo < hi) {
+        const int64_t mid = lo + ((hi - lo) >> 1);
+        if (draw_point<KIND>(mid, delta, seed, instance, u_sys) < c) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// ------------------------------------------------------ phase 1: tile
+__device__ inline void tile_reduce_body(const float *__restrict__ lw, int64_t P, int64_t t,
+                                        char *ws_raw)
+{
+    __shared__ double redd[kNW];
+    __shared__ float redf[kNW];
+    __shared__ int redi[kNW];
+    const WsView ws = ws_view(ws_raw, P);
+    float v[4];
+    load_tile4(lw, P, t, v);
+    int fl = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (isnan(v[k])) fl |= kFlagNan;
+        else if (isinf(v[k]) && v[k] > 0.0f) fl |= kFlagPosInf;
+    }
+    const float mx = block_max(fmaxf(fmaxf(v[0], v[1]), fmaxf(v[2], v[3])), redf);
+    fl = block_or(fl, redi);
+    double s = 0.0;
+    if (mx > -INFINITY) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s += exp((double)v[k] - (double)mx);
+    }
+    s = block_sum(s, redd);
+    if (threadIdx.x == 0) {
+        ws.tile_max[t] = mx;
+        ws.tile_sum[t] = s;
+        ws.tile_flags[t] = fl;
+    }
+}
+
+// ------------------------------------------------------ phase 2: table
+// Global max, tile boundaries B_t (scaled tile sums, scanned, then made
+// non-decreasing by a running maximum), and for stratified/systematic the
+// draw counts below each boundary and the fill layout: one block per tile
+// plus one per further kChunk draws. `bound` and `count` are scratch for n
+// tiles (LDS when they fit, else the workspace arrays themselves).
+template <int KIND>
+__device__ void table_body(int64_t P, uint64_t seed, uint32_t instance, char *ws_raw,
+                           int32_t *status, double *lse_out, double *bound, int32_t *count,
+                           double eps = 0.0, uint32_t B_max = 0, uint32_t *B_used = nullptr)
+{
+    __shared__ double redd[kNW];
+    __shared__ float redf[kNW];
+    __shared__ int redi[kNW];
+    __shared__ int64_t redl[kNW];
+    __shared__ double sh_W;
+    const WsView ws = ws_view(ws_raw, P);
+    WsHeader *h = ws.h;
+    const int64_t n = num_tiles(P);
+    const int tid = threadIdx.x;
+    const bool staged = bound != ws.bound;
+    const int64_t per = (n + kTileThreads - 1) / kTileThreads;
+    const int64_t t0 = min(n, (int64_t)tid * per), t1 = min(n, t0 + per);
+
+    int fl = 0;
+    float m = -INFINITY;
+    for (int64_t t = t0; t < t1; ++t) {
+        fl |= ws.tile_flags[t];
+        m = fmaxf(m, ws.tile_max[t]);
+        bound[t] = ws.tile_sum[t];
+    }
+    fl = block_or(fl, redi);
+    m = block_max(m, redf);
+    if (!(m > -INFINITY)) fl |= kFlagAllNegInf;
+    if (fl) {
+        if (tid == 0) {
+            h->flags = fl;
+            h->n_overflow = 0;
+            h->B = 0;
+            if (B_used) *B_used = 0;
+            if (lse_out)
+                *lse_out = (fl & (kFlagNan | kFlagPosInf)) ? (double)NAN : -(double)INFINITY;
+            raise_flags(status, fl);
+        }
+        return;
+    }
+    double local = 0.0;
+    for (int64_t t = t0; t < t1; ++t) {
+        const float mt = ws.tile_max[t];
+        const double S = (mt > -INFINITY) ? bound[t] * exp((double)mt - (double)m) : 0.0;
+        bound[t] = S;
+        local += S;
+    }
+    double run = block_exclusive_sum(local, redd);
+    double tmax = 0.0;
+    for (int64_t t = t0; t < t1; ++t) {
+        run += bound[t];
+        bound[t] = run;
+        tmax = run;  // running sums grow within a thread
+    }
+    const double carry = block_exclusive_max(tmax, redd);
+    for (int64_t t = t0; t < t1; ++t) {
+        const double b = fmax(bound[t], carry);
+        bound[t] = b;
+        if (staged) ws.bound[t] = b;
+        if (t == n - 1) sh_W = b;
+    }
+    __syncthreads();
+    const double W = sh_W;
+    const double delta = W / (double)P;
+
+    if (KIND == kStratified || KIND == kSystematic) {
+        const double u_sys = KIND == kSystematic ? systematic_offset(seed, instance) : 0.0;
+        for (int64_t t = t0; t < t1; ++t) {
+            const int32_t cnt =
+                (int32_t)count_below<KIND>(bound[t], P, W, delta, seed, instance, u_sys);
+            count[t] = cnt;
+            if (staged) ws.count[t] = cnt;
+        }
+        __syncthreads();  // the previous thread's last count is visible
+        int64_t nov = 0;
+        for (int64_t t = t0; t < t1; ++t) {
+            const int64_t lo = t > 0 ? count[t - 1] : 0, hi = count[t];
+            const int64_t span = hi - (lo & ~(int64_t)3);
+            nov += span > kChunk ? (span + kChunk - 1) / kChunk - 1 : 0;
+        }
+        int64_t tot_ov;
+        int64_t acc = block_exclusive_isum(nov, redl, &tot_ov);
+        for (int64_t t = t0; t < t1; ++t) {
+            ws.overflow[t] = (int32_t)acc;
+            const int64_t lo = t > 0 ? count[t - 1] : 0, hi = count[t];
+            const int64_t span = hi - (lo & ~(int64_t)3);
+            acc += span > kChunk ? (span + kChunk - 1) / kChunk - 1 : 0;
+        }
+        if (tid == 0) {
+            ws.overflow[n] = (int32_t)tot_ov;
+            h->n_overflow = (int32_t)tot_ov;
+            if (tot_ov > max_overflow_chunks(P)) raise_flags(status, kFlagInternal);
+        }
+    }
+    if (tid == 0) {
+        h->m = m;
+        h->W = W;
+        h->delta = delta;
+        h->lse = (double)m + log(W);
+        h->flags = 0;
+        if (lse_out) *lse_out = h->lse;
+        if (KIND == kAdaptiveB) {
+            // with m the largest log-weight the largest normalised weight is 1 / W
+            const uint32_t Bn = iterations_for(P, 1.0 / W, eps);
+            h->B = Bn < B_max ? Bn : B_max;
+            if (B_used) *B_used = h->B;
+        }
+    }
+}
+
+// In-tile cumulative weights C'_j from the thread's four log-weights v:
+// C'_j = min(Blo + L_j, Bhi), with L the zero-weight-aware running maximum of
+// the tile's scan, and C'_j = Bhi from the tile's last positive weight on.
+__device__ inline void tile_cumulative(const float v[4], float m, double Blo, double Bhi,
+                                       double *Cs, double Cout[4])
+{
+    __shared__ double red[kNW];
+    __shared__ double sh_total;
+    double w[4], L[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w[k] = exp((double)v[k] - (double)m);
+    L[0] = w[0];
+    L[1] = L[0] + w[1];
+    L[2] = L[1] + w[2];
+    L[3] = L[2] + w[3];
+    const double prefix = block_exclusive_sum(L[3], red);
+    double V[4];
+    double run = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (w[k] > 0.0) run = prefix + L[k];  // a zero weight repeats its predecessor
+        V[k] = run;
+    }
+    const double carry = block_exclusive_max(run, red);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) V[k] = fmax(V[k], carry);
+    if (threadIdx.x == kTileThreads - 1) sh_total = V[3];
+    __syncthreads();
+    const double Ltot = sh_total;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double C = (V[k] == Ltot) ? Bhi : fmin(Blo + V[k], Bhi);
+        Cout[k] = C;
+        Cs[4 * threadIdx.x + k] = C;
+    }
+    __syncthreads();
+}
+
+// First index j of the kTile-entry Cs with Cs[j] > x (Cs is non-decreasing).
+__device__ __forceinline__ int search_tile(const double *Cs, double x)
+{
+    int j = 0;
+#pragma unroll
+    for (int step = kTile / 2; step >= 1; step >>= 1)
+        if (Cs[j + step - 1] <= x) j += step;
+    return j;
+}
+
+__device__ __forceinline__ void store_cumw(double *cumw, int64_t P, int64_t t, const double C[4])
+{
+    const int64_t base = t * kTile + 4 * (int64_t)threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (base + k < P) cumw[base + k] = C[k];
+}
+
+// Rows x_out[o, :] = x_in[a_o, :] for o in [ob, oe), a_o = sh_anc[o - a0],
+// copied by the whole block (coalesced 16-byte vectors when possible).
+__device__ inline void copy_rows_from_lds(const int32_t *sh_anc, int64_t a0, int64_t ob,
+                                          int64_t oe, const float *__restrict__ x_in,
+                                          float *__restrict__ x_out, int32_t D, int64_t P,
+                                          int *fl)
+{
+    const bool vec = (D % 4 == 0) && ((((uintptr_t)x_in) | ((uintptr_t)x_out)) & 15) == 0;
+    if (vec) {
+        const int cols = D / 4;
+        const int64_t total = (oe - ob) * cols;
+        for (int64_t e = threadIdx.x; e < total; e += kTileThreads) {
+            const int64_t r = e / cols, c = e - r * cols;
+            const int64_t o = ob + r;
+            const int32_t a = sh_anc[o - a0];
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (a >= 0 && (int64_t)a < P) v = reinterpret_cast<const float4 *>(x_in)[(int64_t)a * cols + c];
+            else *fl |= kFlagBadAncestor;
+            reinterpret_cast<float4 *>(x_out)[o * cols + c] = v;
+        }
+    } else {
+        const int64_t total = (oe - ob) * D;
+        for (int64_t e = threadIdx.x; e < total; e += kTileThreads) {
+            const int64_t r = e / D, d = e - r * D;
+            const int64_t o = ob + r;
+            const int32_t a = sh_anc[o - a0];
+            const bool ok = a >= 0 && (int64_t)a < P;
+            x_out[o * D + d] = ok ? x_in[(int64_t)a * D + d] : 0.0f;
+            if (!ok) *fl |= kFlagBadAncestor;
+        }
+    }
+}
+
+// ------------------------------------------------------ phase 3: fill
+// Fill block g of an instance: tile g (g < n) or an extra chunk of a heavy
+// tile. Writes the block's ancestors (and, with x_in, copies their rows).
+// Cs: kTile doubles, sh_anc: kChunk ints of LDS.
+template <int KIND>
+__device__ void fill_body(const float *__restrict__ lw, int32_t *__restrict__ anc, int64_t P,
+                          uint64_t seed, uint32_t instance, double *cumw, char *ws_raw, int64_t g,
+                          const float *x_in, float *x_out, int32_t D, int32_t *status, double *Cs,
+                          int32_t *sh_anc)
+{
+    const WsView ws = ws_view(ws_raw, P);
+    const int64_t n = num_tiles(P);
+    int64_t t = g, c = 0;
+    float v[4];
+    // every read this block needs is issued up front (one memory round trip)
+    const int64_t tq = g < n ? g : n - 1;
+    load_tile4(lw, P, tq, v);
+    const int flags = ws.h->flags;
+    const int n_ov = ws.h->n_overflow;
+    const double delta = ws.h->delta;
+    const float m = ws.h->m;
+    int64_t lo = tq > 0 ? ws.count[tq - 1] : 0, hi = ws.count[tq];
+    double Blo = tq > 0 ? ws.bound[tq - 1] : 0.0, Bhi = ws.bound[tq];
+    if (flags) {  // flagged input: identity ancestors (rows copied in place order)
+        if (g < n) {
+            for (int64_t j = g * kTile + threadIdx.x; j < min(P, (g + 1) * kTile); j += kTileThreads) {
+                anc[j] = (int32_t)j;
+                if (cumw) cumw[j] = (double)NAN;
+                if (x_in)
+                    for (int d = 0; d < D; ++d) x_out[j * D + d] = x_in[j * D + d];
+            }
+        }
+        return;
+    }
+    if (g >= n) {
+        const int64_t q = g - n;
+        if (q >= n_ov) return;
+        int64_t a = 0, z = n - 1;  // last t with overflow[t] <= q
+        while (a < z) {
+            const int64_t mid = (a + z + 1) >> 1;
+            if (ws.overflow[mid] <= q) a = mid;
+            else z = mid - 1;
+        }
+        t = a;
+        c = q - ws.overflow[t] + 1;
+        load_tile4(lw, P, t, v);
+        lo = t > 0 ? ws.count[t - 1] : 0;
+        hi = ws.count[t];
+        Blo = t > 0 ? ws.bound[t - 1] : 0.0;
+        Bhi = ws.bound[t];
+    }
+    const int64_t a0 = (lo & ~(int64_t)3) + c * kChunk;
+    const int64_t ob = max(lo, a0), oe = min(hi, a0 + kChunk);
+    if (ob >= oe && !(cumw && c == 0)) return;  // nothing to write
+
+    double C[4];
+    tile_cumulative(v, m, Blo, Bhi, Cs, C);  // ends with a barrier
+    if (cumw && c == 0) store_cumw(cumw, P, t, C);
+
+    const int64_t o0 = a0 + 8 * (int64_t)threadIdx.x;
+    if (o0 + 8 > ob && o0 < oe) {
+        double U[8];
+        if (KIND == kStratified) {
+            const Block4 b0 = philox(seed, (uint32_t)(o0 >> 2), instance, 0u, kTagStratified);
+            const Block4 b1 = philox(seed, (uint32_t)(o0 >> 2) + 1u, instance, 0u, kTagStratified);
+            U[0] = unit32(b0.r0); U[1] = unit32(b0.r1); U[2] = unit32(b0.r2); U[3] = unit32(b0.r3);
+            U[4] = unit32(b1.r0); U[5] = unit32(b1.r1); U[6] = unit32(b1.r2); U[7] = unit32(b1.r3);
+        } else {
+            const double u_sys = systematic_offset(seed, instance);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) U[k] = u_sys;
+        }
+        const double cap = below(Bhi);
+        int32_t a[8];
+        const int32_t tile_base = (int32_t)(t * kTile);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const double x = ((double)(o0 + k) + U[k]) * delta;
+            a[k] = tile_base + search_tile(Cs, fmin(x, cap));
+        }
+        const bool full = (o0 >= ob) && (o0 + 8 <= oe) && ((((uintptr_t)anc) & 15) == 0);
+        if (full) {
+            int4 *dst = reinterpret_cast<int4 *>(anc + o0);
+            dst[0] = make_int4(a[0], a[1], a[2], a[3]);
+            dst[1] = make_int4(a[4], a[5], a[6], a[7]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (o0 + k >= ob && o0 + k < oe) anc[o0 + k] = a[k];
+        }
+        if (x_in) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) sh_anc[8 * threadIdx.x + k] = a[k];
+        }
+    }
+    if (x_in) {
+        __syncthreads();
+        int fl = 0;
+        copy_rows_from_lds(sh_anc, a0, ob, oe, x_in, x_out, D, P, &fl);
+        raise_flags(status, fl);
+    }
+}
+
+}  // namespace pfx
+}  // namespace rs

@@ -1,0 +1,124 @@
+"""GPU batched resampling: every instance of a batch equals its single call
+bit for bit (ancestors and copied rows), under several tunings and across
+graph replays; a sample of instances also matches the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1202_6163_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rs():
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    import paper_1202_6163_amd.api as api
+    return api
+
+
+def make_instances(n, p_lo, p_hi, D, seed, with_copy=True):
+    P, sig = workloads.batch_instances(n, seed=seed, p_lo=p_lo, p_hi=p_hi)
+    rng = np.random.default_rng(seed + 7)
+    kinds = rng.choice(["metropolis", "stratified", "systematic"], size=n)
+    insts = []
+    for k in range(n):
+        Pk = int(P[k])
+        if k == 3:
+            Pk = 0  # an empty instance
+        lw = torch.from_numpy(workloads.normal_logweights(Pk, sig[k], 100 + k)).cuda()
+        d = dict(lw=lw, anc=torch.full((Pk,), -7, dtype=torch.int32, device="cuda"),
+                 kind=str(kinds[k]), B=int(rng.integers(1, 80)), seed=1000 + k,
+                 instance=k, status=torch.zeros(1, dtype=torch.int32, device="cuda"))
+        if with_copy and k % 5 != 1:
+            Dk = D if k % 3 else 3  # some rows of a width the vector path cannot take
+            d["x_in"] = torch.from_numpy(workloads.state_rows_exact(Pk, Dk)).cuda()
+            d["x_out"] = torch.zeros_like(d["x_in"])
+        insts.append(d)
+    return insts
+
+
+def single(rs, d):
+    lw = d["lw"]
+    if d["kind"] == "metropolis":
+        anc = rs.resample_metropolis(lw, d["B"], d["seed"], d["instance"])
+    else:
+        anc = getattr(rs, f"resample_{d['kind']}")(lw, d["seed"], d["instance"])
+    out = rs.permute_copy(anc, d["x_in"]) if "x_in" in d else None
+    return anc, out
+
+
+def check_batch(rs, insts):
+    for k, d in enumerate(insts):
+        anc, out = single(rs, d)
+        assert torch.equal(d["anc"], anc), f"instance {k} ({d['kind']}, P={d['lw'].numel()})"
+        if out is not None:
+            assert torch.equal(d["x_out"].view(torch.int32), out.view(torch.int32)), k
+        assert int(d["status"].item()) == 0
+
+
+TUNINGS = [None, dict(chains_per_item=256, unroll=2, lds_max_p=0, blocks=7),
+           dict(chains_per_item=2048, unroll=16, lds_max_p=32768, blocks=0),
+           dict(chains_per_item=512, unroll=4, lds_max_p=16384, blocks=64)]
+
+
+@pytest.mark.parametrize("tuning", TUNINGS)
+def test_batch_equals_single_calls(rs, tuning):
+    from paper_1202_6163_amd.batch import Batch
+    insts = make_instances(48, 6, 14, 16, seed=1)
+    b = Batch(insts, tuning=tuning)
+    b.run()
+    torch.cuda.synchronize()
+    check_batch(rs, insts)
+
+
+def test_batch_matches_oracle_sample(rs):
+    from paper_1202_6163_amd.batch import Batch
+    insts = make_instances(12, 8, 13, 4, seed=2)
+    Batch(insts).run()
+    torch.cuda.synchronize()
+    for d in insts:
+        lw = d["lw"].cpu().numpy()
+        if lw.size == 0:
+            continue
+        if d["kind"] == "metropolis":
+            ref, _ = oracle.metropolis(lw, d["B"], d["seed"], d["instance"])
+            assert np.array_equal(d["anc"].cpu().numpy(), ref)
+        else:
+            ref, _ = getattr(oracle, d["kind"])(lw, d["seed"], d["instance"])
+            assert np.count_nonzero(d["anc"].cpu().numpy() != ref) <= 2
+
+
+def test_batch_full_workload_and_graph_replays(rs):
+    # 1024 instances, P log-uniform in [2^8, 2^16], Metropolis B = 64 and
+    # stratified, D = 16
+    from paper_1202_6163_amd.batch import Batch
+    P, sig = workloads.batch_instances(1024, seed=0)
+    insts = []
+    for k in range(1024):
+        Pk = int(P[k])
+        lw = torch.from_numpy(workloads.normal_logweights(Pk, sig[k], k)).cuda()
+        insts.append(dict(lw=lw, anc=torch.empty(Pk, dtype=torch.int32, device="cuda"),
+                          kind="metropolis" if k % 2 else "stratified", B=64, seed=5, instance=k,
+                          x_in=torch.from_numpy(workloads.state_rows_normal(Pk, 16, k)).cuda(),
+                          x_out=torch.empty((Pk, 16), dtype=torch.float32, device="cuda"),
+                          status=torch.zeros(1, dtype=torch.int32, device="cuda")))
+    b = Batch(insts)
+    b.run()
+    torch.cuda.synchronize()
+    check_batch(rs, insts)
+    ref = [d["anc"].clone() for d in insts]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        b.run()
+    for rep in range(3):
+        for d in insts:
+            d["anc"].fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for k, d in enumerate(insts):
+            assert torch.equal(d["anc"], ref[k]), (rep, k)

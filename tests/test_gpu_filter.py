@@ -1,0 +1,65 @@
+"""GPU bootstrap filter: the propagate/weight kernels against the oracle, and
+the full filter's log-likelihood against the Kalman closed form (the workload
+P = 2^18, D = 8, T = 200)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle.kalman import kalman_loglik
+from paper_1202_6163_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rs():
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    import paper_1202_6163_amd.api as api
+    return api
+
+
+def test_filter_init_and_step_match_oracle(rs):
+    for P, D in ((1000, 8), (777, 3), (4096, 4)):
+        A = workloads.filter_model(D=D, seed=1)
+        x = torch.empty((P, D), dtype=torch.float32, device="cuda")
+        rs.filter_init(x, seed=5)
+        x0 = oracle.filter_init(P, D, seed=5)
+        np.testing.assert_allclose(x.cpu().numpy(), x0, rtol=1e-6, atol=1e-6)
+        y = np.linspace(-1, 1, D).astype(np.float32)
+        x1_o, lw_o = oracle.filter_step(x0, A, y, 0.1, 0.5, seed=5, t=3)
+        x1, lw = rs.filter_propagate_weight(torch.from_numpy(x0).cuda(),
+                                            torch.from_numpy(A).cuda(),
+                                            torch.from_numpy(y).cuda(), 0.1, 0.5, 5, 3)
+        np.testing.assert_allclose(x1.cpu().numpy(), x1_o, rtol=1e-6, atol=1e-6)
+        np.testing.assert_allclose(lw.cpu().numpy(), lw_o, rtol=1e-6, atol=1e-5)
+
+
+# A fixed small B biases the Metropolis resampler (Sec. 2): in this model the
+# iterations eq. (5) asks for swing between ~100 and ~6000 from step to step,
+# so the Metropolis filter uses the adaptive B (eq. (5) per step, eps = 0.01).
+@pytest.mark.parametrize("resampler,B", [("stratified", 0), ("metropolis_adaptive", 16384)])
+def test_filter_loglik_matches_kalman(resampler, B):
+    from paper_1202_6163_amd.filter import BootstrapFilter
+    A = workloads.filter_model(D=8, seed=0)
+    y = workloads.filter_observations(A, T=200, seed=0)
+    ll_true = kalman_loglik(A, y, 0.1, 0.5)
+    lls = np.array([BootstrapFilter(A, 1 << 18, seed=s, resampler=resampler, B=B).run(y, graph=True)
+                    for s in range(10)])
+    var = lls.var(ddof=1)
+    print(f"{resampler}: mean loglik {lls.mean():.3f} sd {np.sqrt(var):.3f} kalman {ll_true:.3f}",
+          flush=True)
+    # E[log Z_hat] = log Z - var/2 to first order; 4 standard errors
+    assert abs(lls.mean() + var / 2 - ll_true) <= 4 * np.sqrt(var / 10) + 0.05
+
+
+def test_filter_small_matches_oracle_in_distribution():
+    # GPU and oracle filters at small P: both unbiased for Z, so their
+    # log-likelihood estimates agree within Monte Carlo error
+    from paper_1202_6163_amd.filter import BootstrapFilter
+    A = workloads.filter_model(D=8, seed=0)
+    y = workloads.filter_observations(A, T=30, seed=2)
+    g = np.array([BootstrapFilter(A, 2048, seed=s).run(y) for s in range(12)])
+    o = np.array([oracle.bootstrap_filter(A, y, 2048, 0.1, 0.5, seed=s) for s in range(12)])
+    se = np.sqrt(g.var(ddof=1) / 12 + o.var(ddof=1) / 12)
+    assert abs(g.mean() - o.mean()) <= 4 * se + 0.02

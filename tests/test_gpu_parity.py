@@ -134,6 +134,24 @@ def test_metropolis_full_size(rs, B, sigma):
         assert np.array_equal(anc[idx], ref)
 
 
+@pytest.mark.parametrize("P,sigma", [(1000, 0.5), (4097, 2.0), (1 << 18, 1.0)])
+def test_metropolis_adaptive_B(rs, P, sigma):
+    lw = workloads.normal_logweights(P, sigma, 11)
+    C, _, _ = oracle.cumulative(lw)
+    for eps, B_max in ((0.01, 4096), (1e-3, 64)):
+        B_ref = min(oracle.metropolis_B(P, 1.0 / C[-1], eps), B_max)
+        B_used = torch.zeros(1, dtype=torch.int32, device="cuda")
+        anc = host(rs.resample_metropolis_adaptive(dev(lw), 3, 1, eps=eps, B_max=B_max,
+                                                   B_used=B_used))
+        assert int(host(B_used)[0]) == B_ref
+        if P <= 4097 or B_ref <= 64:
+            ref, _ = oracle.metropolis(lw, B_ref, 3, 1)
+            assert np.array_equal(anc, ref)
+        else:
+            idx = np.arange(0, P, 97)
+            assert np.array_equal(anc[idx], oracle.metropolis_subset(lw, B_ref, 3, 1, idx))
+
+
 def test_metropolis_deterministic(rs):
     lw = dev(workloads.normal_logweights(1 << 18, 1.0, 5))
     a = host(rs.resample_metropolis(lw, 64, 9, 1))

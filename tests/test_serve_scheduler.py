@@ -1,0 +1,121 @@
+"""Serving scheduler on the CPU with a fake executor and a fake clock:
+admission by device footprint, FIFO order, continuous batching (requests that
+arrive while others run are admitted and started as memory and streams free
+up), rejection of oversize requests, latency bookkeeping."""
+import pytest
+
+from paper_1202_6163_amd.serve import Request, Scheduler, footprint, summarize
+
+
+class Clock:
+    def __init__(self):
+        self.t = 0.0
+
+
+class FakeExecutor:
+    def __init__(self, clock, n_streams=2, per_particle=1e-9, overhead=5e-5):
+        self.clock, self.n_streams = clock, n_streams
+        self.per_particle, self.overhead = per_particle, overhead
+        self.admitted, self.released, self.submitted = [], [], []
+
+    def admit(self, r):
+        self.admitted.append(r.id)
+
+    def release(self, r):
+        self.released.append(r.id)
+
+    def submit(self, s, reqs):
+        t_end = self.clock.t + self.overhead + self.per_particle * sum(r.P for r in reqs)
+        self.submitted.append((self.clock.t, s, [r.id for r in reqs]))
+        return {"t_end": t_end}
+
+    def poll(self, h):
+        return self.clock.t >= h["t_end"]
+
+    def finished_time(self, h):
+        return h["t_end"]
+
+
+def run(sched, reqs, clock, dt=1e-5, until=10.0):
+    i = 0
+    reqs = sorted(reqs, key=lambda r: r.t_arrival)
+    max_used = 0
+    while (i < len(reqs) or not sched.idle()) and clock.t < until:
+        while i < len(reqs) and reqs[i].t_arrival <= clock.t:
+            sched.arrive(reqs[i])
+            i += 1
+        sched.step(clock.t)
+        max_used = max(max_used, sched.used)
+        assert sched.used <= sched.budget
+        clock.t += dt
+    return max_used
+
+
+def mk(n, P=100000, gap=1e-4, D=16, kind="stratified"):
+    return [Request(id=k, t_arrival=k * gap, P=P, kind=kind, D=D) for k in range(n)]
+
+
+def test_all_complete_fifo_and_budget():
+    clock = Clock()
+    ex = FakeExecutor(clock)
+    reqs = mk(50)
+    budget = 4 * footprint(reqs[0]) + 10
+    sched = Scheduler(ex, budget)
+    peak = run(sched, reqs, clock)
+    assert len(sched.done) == 50 and sched.idle()
+    assert ex.admitted == list(range(50))  # first come, first admitted
+    assert peak <= budget and sched.peak_used <= budget
+    assert sorted(ex.released) == list(range(50))
+    assert sched.used == 0
+    for r in sched.done:
+        assert r.t_arrival <= r.t_admit <= r.t_start < r.t_done
+
+
+def test_continuous_batching_overlaps_streams():
+    clock = Clock()
+    ex = FakeExecutor(clock, n_streams=2, per_particle=1e-8)
+    reqs = mk(6, P=200000, gap=2e-4)
+    sched = Scheduler(ex, 1 << 40)
+    run(sched, reqs, clock)
+    # request 1 arrives while batch 0 runs and starts on the other stream
+    # before batch 0 ends
+    (t0, s0, ids0), (t1, s1, ids1) = ex.submitted[0], ex.submitted[1]
+    assert ids0 == [0] and s1 != s0 and t1 < sched.done[0].t_done
+    # later arrivals join batches as streams free up; nothing waits for a
+    # whole static batch to finish
+    assert len(ex.submitted) >= 3
+    assert sum(len(b) for _, _, b in ex.submitted) == 6
+
+
+def test_admission_waits_for_memory():
+    clock = Clock()
+    ex = FakeExecutor(clock, n_streams=4, per_particle=1e-8)
+    reqs = mk(8, P=500000, gap=1e-6)
+    budget = 2 * footprint(reqs[0])
+    sched = Scheduler(ex, budget)
+    run(sched, reqs, clock)
+    assert len(sched.done) == 8
+    waits = [r.t_admit - r.t_arrival for r in sched.done]
+    assert max(waits) > 0.005  # later requests waited for memory to free up
+    s = summarize(sched, duration=1.0)
+    assert s["requests"] == 8 and s["p99_admission_wait_ms"] > 5
+
+
+def test_oversize_request_rejected_and_batch_caps():
+    clock = Clock()
+    ex = FakeExecutor(clock)
+    small = mk(3, P=1000)
+    big = Request(id=99, t_arrival=0.0, P=1 << 20, kind="metropolis", D=16)
+    sched = Scheduler(ex, 10 * footprint(small[0]), max_batch=2)
+    run(sched, small + [big], clock)
+    assert [r.id for r in sched.rejected] == [99]
+    assert len(sched.done) == 3
+    assert all(len(ids) <= 2 for _, _, ids in ex.submitted)
+
+
+def test_footprint_counts_state_and_workspace():
+    r1 = Request(id=0, t_arrival=0, P=4096, kind="metropolis", D=0)
+    r2 = Request(id=1, t_arrival=0, P=4096, kind="stratified", D=0)
+    r3 = Request(id=2, t_arrival=0, P=4096, kind="stratified", D=16)
+    assert footprint(r2) > footprint(r1)
+    assert footprint(r3) - footprint(r2) == 8 * 4096 * 16
