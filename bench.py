@@ -65,43 +65,7 @@ def parse():
     return ap.parse_args()
 
 
-def pct(a, q):
-    return float(np.percentile(np.asarray(a), q))
-
-
-class Graphs:
-    """Calls captured into HIP graphs (torch.cuda.CUDAGraph on the library's
-    stream) and replayed back to back with a HIP event between replays, so the
-    GPU never waits for the host: interval k = replay k's GPU time."""
-
-    def __init__(self, torch):
-        self.torch = torch
-
-    def capture(self, fn):
-        torch = self.torch
-        s = torch.cuda.Stream()
-        s.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(s):
-            fn()  # warm-up outside the capture (sets kernel attributes)
-        torch.cuda.current_stream().wait_stream(s)
-        torch.cuda.synchronize()
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g):
-            fn()
-        torch.cuda.synchronize()
-        return g
-
-    def replay_ms(self, graphs, n):
-        """Replay graphs[k % len] for k < n; returns the n intervals in ms."""
-        torch = self.torch
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
-        graphs[0].replay()  # prime the queue so the first interval is GPU-bound
-        ev[0].record()
-        for k in range(n):
-            graphs[k % len(graphs)].replay()
-            ev[k + 1].record()
-        torch.cuda.synchronize()
-        return [ev[k].elapsed_time(ev[k + 1]) for k in range(n)]
+from paper_1202_6163_amd.timing import Graphs, pct  # noqa: E402
 
 
 def main():
@@ -145,7 +109,10 @@ def main():
 
     if args.only:
         # profiling mode: plain launches of one kernel family on the cold sets
+        big = torch.empty(1 << 24, dtype=torch.float32, device=dev)  # 64 MiB
+        big_out = torch.empty_like(big)
         only = {"metropolis": lambda bs, k: rs.resample_metropolis(bs["lw"], B, k, 0, anc=bs["anc"]),
+                "copycal": lambda bs, k: big_out.copy_(big),
                 "stratified": lambda bs, k: rs.resample_stratified(bs["lw"], k, 0, anc=bs["anc"], ws=ws),
                 "copy": lambda bs, k: rs.permute_copy(bs["anc"], bs["x"], x_out=bs["xo"]),
                 "step": lambda bs, k: step(bs, k, 0)}[args.only]
@@ -413,16 +380,17 @@ def batched(torch, rs, workloads, args):
 
 
 def filter_run(torch, workloads, args):
-    """Bootstrap filter, D = 8, T = 200, P = 2^18, stratified resampling every
-    step, one HIP graph per run; log-likelihood against the Kalman filter."""
+    """Bootstrap filter, D = 8, T = 200, P = 2^18, resampling every step
+    (stratified; Metropolis with B from eq. (5) per step), one HIP graph per
+    run; log-likelihood against the Kalman filter."""
     from oracle.kalman import kalman_loglik
     from paper_1202_6163_amd.filter import BootstrapFilter
     A = workloads.filter_model(D=8, seed=0)
     y = workloads.filter_observations(A, T=200, seed=0)
     ll_true = kalman_loglik(A, y, 0.1, 0.5)
     res = {"P": 1 << 18, "D": 8, "T": 200, "kalman_loglik": ll_true}
-    for resampler in ("stratified", "metropolis"):
-        f = BootstrapFilter(A, 1 << 18, seed=1, resampler=resampler, B=64)
+    for resampler in ("stratified", "metropolis_adaptive"):
+        f = BootstrapFilter(A, 1 << 18, seed=1, resampler=resampler, B=16384)
         yd = torch.as_tensor(y, device="cuda")
         lse = torch.empty(200, dtype=torch.float64, device="cuda")
         g = f.capture(yd, lse)

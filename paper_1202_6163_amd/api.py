@@ -205,6 +205,21 @@ def rs_metropolis_get_tuning():
                 lanes_per_chain=t.lanes_per_chain)
 
 
+def _apply_stored_tuning():
+    """Launch parameters from the autotuner's table for this device, if any."""
+    from . import autotune
+    try:
+        rec = autotune.load(torch, lib) if torch.cuda.is_available() else None
+    except Exception:  # a missing or unreadable table leaves the defaults
+        rec = None
+    if rec and "metropolis" in rec:
+        rs_metropolis_set_tuning(**rec["metropolis"])
+    return rec
+
+
+_STORED_TUNING = _apply_stored_tuning()
+
+
 RESAMPLERS = {
     "metropolis": resample_metropolis,
     "stratified": resample_stratified,

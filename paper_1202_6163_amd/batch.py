@@ -17,6 +17,15 @@ KINDS = {"metropolis": METROPOLIS, "stratified": STRATIFIED, "systematic": SYSTE
 DEFAULT_TUNING = dict(chains_per_item=1024, unroll=8, lds_max_p=8192, blocks=0)
 
 
+def default_tuning():
+    """The autotuned batch parameters for this device, else the defaults."""
+    from . import api
+    rec = api._STORED_TUNING
+    if rec and "batch" in rec:
+        return dict(rec["batch"])
+    return dict(DEFAULT_TUNING)
+
+
 class Batch:
     def __init__(self, instances, tuning=None, device=None, stream=None, async_upload=False):
         """instances: dicts with lw, anc, kind ('metropolis' | 'stratified' |
@@ -50,7 +59,7 @@ class Batch:
                                    KINDS[d["kind"]], int(d.get("B", 0)), int(d["instance"]),
                                    int(d["seed"]))
         self._arr = arr
-        t = dict(DEFAULT_TUNING, **(tuning or {}))
+        t = dict(default_tuning(), **(tuning or {}))
         self.tuning = _lib.BatchTuning(t["chains_per_item"], t["unroll"], t["lds_max_p"],
                                        t["blocks"])
         pb = lib.rs_batch_plan_bytes(arr, n, ctypes.byref(self.tuning))
