@@ -3,8 +3,9 @@
 Step (the timed unit): one pass of the whole resampling path over one batch
 of P = 2^20 particles with log-weights N(0, sigma^2) (sigma = 1) and D = 4
 binary32 state rows: the Metropolis (B = 32), stratified, systematic and
-multinomial resamplers, each followed by the offspring conversion and the
-ancestor-indexed state copy. Every step uses the next of several rotating
+multinomial resamplers, each in the paper's output form (offspring for
+stratified and systematic, ancestors for the other two) and each followed by
+the ancestor-indexed state copy. Every step uses the next of several rotating
 input/output buffer sets whose total exceeds the 256 MB Infinity Cache, so
 the step reads its inputs from HBM. value = resampled particles per second
 (4 P per step) at the p99 step time.
@@ -97,15 +98,17 @@ def main():
     set_bytes = sum(t.numel() * t.element_size() for t in sets[0].values())
 
     def step(bs, seed, inst):
-        for name, fn in (("metropolis", None), ("stratified", rs.resample_stratified),
-                         ("systematic", rs.resample_systematic),
-                         ("multinomial", rs.resample_multinomial)):
-            if fn is None:
-                rs.resample_metropolis(bs["lw"], B, seed, inst, anc=bs["anc"], status=status)
-            else:
-                fn(bs["lw"], seed, inst, anc=bs["anc"], ws=ws, status=status)
+        # Each resampler in the paper's output form (Sec. 2: stratified and
+        # systematic give offspring, multinomial and Metropolis ancestors),
+        # then the ancestor-indexed state copy.
+        rs.resample_metropolis(bs["lw"], B, seed, inst, anc=bs["anc"], status=status)
+        rs.permute_copy(bs["anc"], bs["x"], x_out=bs["xo"], status=status)
+        for fn in (rs.resample_stratified, rs.resample_systematic):
+            fn(bs["lw"], seed, inst, anc=bs["anc"], ws=ws, status=status)
             rs.ancestors_to_offspring(bs["anc"], off=bs["off"], status=status)
             rs.permute_copy(bs["anc"], bs["x"], x_out=bs["xo"], status=status)
+        rs.resample_multinomial(bs["lw"], seed, inst, anc=bs["anc"], ws=ws, status=status)
+        rs.permute_copy(bs["anc"], bs["x"], x_out=bs["xo"], status=status)
 
     if args.only:
         # profiling mode: plain launches of one kernel family on the cold sets
@@ -176,6 +179,7 @@ def main():
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dominant,
                     "avg_launch_us": means[dominant] * 1e3}
+    roofline["measured_ceilings"] = ceilings(torch, rs, G, sets[0]["lw"], iters / (means["metropolis"] * 1e-3))
     copy_gbs = (4 + 8 * D) * P / (np.mean(copy_ms) * 1e-3) / 1e9
     strat_gbs = 12 * P / (np.mean(strat_ms) * 1e-3) / 1e9
     path_gbs = (12 + 4 + 8 * D) * P / ((np.mean(copy_ms) + np.mean(strat_ms)) * 1e-3) / 1e9
@@ -199,8 +203,9 @@ def main():
         "vs_baseline": None, "dtype": "f32 weights / f64 prefix sums / u32 Philox",
         "data": "synthetic", "config": {
             "workload": "resampler sweep point P=2^20, lw ~ N(0, 1), D=4 state copy; step = "
-                        "Metropolis(B=32) + stratified + systematic + multinomial, each with "
-                        "offspring + copy; cold HBM (rotating buffer sets)",
+                        "Metropolis(B=32) + stratified + systematic + multinomial, each followed "
+                        "by the state copy, offspring for stratified/systematic; cold HBM "
+                        "(rotating buffer sets)",
             "P": P, "D": D, "sigma": sigma, "B": B, "buffer_sets": args.sets,
             "set_bytes": set_bytes, "parallelism": "single GPU"},
         "per_call_ms_cold": {k: float(v) for k, v in means.items()},
@@ -222,6 +227,28 @@ def main():
         with open(args.out, "w") as f:
             f.write(line + "\n")
     print(line, flush=True)
+
+
+def ceilings(torch, rs, G, lw, metro_iter_per_s):
+    """Measured device rates for the two halves of a Metropolis iteration:
+    random 4-byte gathers from the P weights (the proposal) and Philox4x32-10
+    blocks (two words per iteration). The iteration rate can exceed neither
+    the gather rate nor twice the block rate."""
+    threads, rounds = 1 << 20, 8
+    out_f = torch.empty(threads, dtype=torch.float32, device=lw.device)
+    out_i = torch.empty(threads, dtype=torch.int32, device=lw.device)
+    g1 = G.capture(lambda: rs.rs_probe_gather(lw, threads, rounds, 1, out=out_f))
+    g2 = G.capture(lambda: rs.rs_probe_philox(threads, rounds, 1, out=out_i))
+    G.replay_ms([g1, g2], 2)
+    gather_ms = float(np.median(G.replay_ms([g1], 10)))
+    philox_ms = float(np.median(G.replay_ms([g2], 10)))
+    gathers = threads * rounds * 8 / (gather_ms * 1e-3)
+    blocks = threads * rounds * 4 / (philox_ms * 1e-3)
+    bound = min(gathers, 2 * blocks)
+    return {"random_gather_per_s": gathers, "philox_blocks_per_s": blocks,
+            "metropolis_iter_per_s": metro_iter_per_s, "iteration_ceiling_per_s": bound,
+            "frac_of_measured_ceiling": metro_iter_per_s / bound,
+            "gather_array_bytes": 4 * lw.numel()}
 
 
 def load_traffic(kernel):

@@ -310,6 +310,20 @@ int rs_metropolis_get_tuning(rs_metropolis_tuning *t);       /* t [host] */
  */
 int rs_log_u_table(float *approx, float *exact, hipStream_t stream);
 
+/*
+ * Measurement probes for the Metropolis roofline (not resamplers). The
+ * gather probe performs threads x rounds x 8 random 4-byte loads from
+ * w[0..n) (xorshift indices through the same index map as the proposals);
+ * the Philox probe computes threads x rounds x 4 Philox4x32-10 blocks. Each
+ * thread writes one folded word to out[threads] [device]. threads is a
+ * multiple of 256. Timing them gives the device's random-gather and Philox
+ * rates, the two ceilings of a Metropolis iteration.
+ */
+int rs_probe_gather(const float *w, int64_t n, int64_t threads, int64_t rounds, uint32_t salt,
+                    float *out, hipStream_t stream);
+int rs_probe_philox(uint64_t seed, int64_t threads, int64_t rounds, uint32_t *out,
+                    hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

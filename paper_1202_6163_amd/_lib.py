@@ -81,6 +81,8 @@ def _load():
         "rs_log_sum_exp": (ctypes.c_int, [vp, i64, vp, vp, sz, i32p, vp]),
         "metropolis_B": (u32, [i64, ctypes.c_double, ctypes.c_double]),
         "rs_log_u_table": (ctypes.c_int, [vp, vp, vp]),
+        "rs_probe_gather": (ctypes.c_int, [vp, i64, i64, i64, u32, vp, vp]),
+        "rs_probe_philox": (ctypes.c_int, [u64, i64, i64, vp, vp]),
         "filter_init": (ctypes.c_int, [vp, i64, ctypes.c_int32, u64, vp]),
         "filter_propagate_weight": (ctypes.c_int, [vp, vp, vp, i64, ctypes.c_int32, vp, vp,
                                                    ctypes.c_double, ctypes.c_double, u64, u32,

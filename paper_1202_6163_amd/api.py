@@ -189,6 +189,24 @@ def rs_log_u_table(approx=None, exact=None, stream=None):
     return approx, exact
 
 
+def rs_probe_gather(w, threads, rounds, salt=1, out=None, stream=None):
+    """Random-gather probe (see include/resample.h); returns out."""
+    _need(w, torch.float32, "w")
+    out = torch.empty(threads, dtype=torch.float32, device=w.device) if out is None else out
+    check(lib.rs_probe_gather(_ptr(w), w.numel(), int(threads), int(rounds), int(salt), _ptr(out),
+                              _stream_handle(stream)), "rs_probe_gather")
+    return out
+
+
+def rs_probe_philox(threads, rounds, seed=1, out=None, stream=None):
+    """Philox-rate probe (see include/resample.h); returns out."""
+    dev = torch.device("cuda", torch.cuda.current_device())
+    out = torch.empty(threads, dtype=torch.int32, device=dev) if out is None else out
+    check(lib.rs_probe_philox(int(seed), int(threads), int(rounds), _ptr(out),
+                              _stream_handle(stream)), "rs_probe_philox")
+    return out
+
+
 def metropolis_B(P, w_max, eps):
     return int(lib.metropolis_B(int(P), float(w_max), float(eps)))
 

@@ -74,7 +74,7 @@ bool layout_of(const rs_instance *d, int32_t n, const rs_batch_tuning &t, Layout
             const int64_t nt = rs::num_tiles(d[k].P);
             tiles += nt;
             tables += 1;
-            mains += nt + rs::max_overflow_chunks(d[k].P);
+            mains += rs::num_fill_blocks(d[k].P);
             L->max_tiles = std::max(L->max_tiles, nt);
         } else {
             mains += (d[k].P + t.chains_per_item - 1) / t.chains_per_item;
@@ -166,7 +166,7 @@ int rs_batch_plan_init(rs_batch_plan *plan, const rs_instance *descs, int32_t n,
             const int64_t tiles = rs::num_tiles(d.P);
             for (int64_t q = 0; q < tiles; ++q) tile_items[nt++] = make_int2(k, (int)q);
             table_items[nb++] = k;
-            const int64_t fills = tiles + rs::max_overflow_chunks(d.P);
+            const int64_t fills = rs::num_fill_blocks(d.P);
             for (int64_t g = 0; g < fills; ++g)
                 mains.push_back({make_int2(k, (int)g), g < tiles ? 4096.0 : 64.0});
         } else {

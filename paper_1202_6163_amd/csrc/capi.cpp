@@ -243,6 +243,25 @@ int rs_log_u_table(float *approx, float *exact, hipStream_t stream)
     return map_rc(rs::launch_log_u_table(approx, exact, stream));
 }
 
+int rs_probe_gather(const float *w, int64_t n, int64_t threads, int64_t rounds, uint32_t salt,
+                    float *out, hipStream_t stream)
+{
+    if (!w || !out || n < 1 || n > kMaxP || threads < 256 || threads % 256 ||
+        threads > (int64_t)1 << 30 || rounds < 1 || rounds > (int64_t)1 << 20)
+        return RS_EINVAL;
+    return map_rc(rs::launch_gather_probe(w, (uint32_t)n, (uint32_t)threads, (uint32_t)rounds, salt,
+                                          out, stream));
+}
+
+int rs_probe_philox(uint64_t seed, int64_t threads, int64_t rounds, uint32_t *out,
+                    hipStream_t stream)
+{
+    if (!out || threads < 256 || threads % 256 || threads > (int64_t)1 << 30 || rounds < 1 ||
+        rounds > (int64_t)1 << 20)
+        return RS_EINVAL;
+    return map_rc(rs::launch_philox_probe(seed, (uint32_t)threads, (uint32_t)rounds, out, stream));
+}
+
 int rs_metropolis_set_tuning(const rs_metropolis_tuning *t)
 {
     if (!t) return RS_EINVAL;

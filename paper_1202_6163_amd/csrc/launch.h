@@ -58,6 +58,11 @@ int launch_permute_copy(const int32_t *anc, const float *x_in, float *x_out, int
 
 int launch_zero(void *ptr, size_t bytes, hipStream_t stream);
 
+int launch_gather_probe(const float *w, uint32_t n, uint32_t threads, uint32_t rounds,
+                        uint32_t salt, float *out, hipStream_t stream);
+int launch_philox_probe(uint64_t seed, uint32_t threads, uint32_t rounds, uint32_t *out,
+                        hipStream_t stream);
+
 // ---------------------------------------------------------------- batches
 constexpr int kMetropolisKind = 3;  // RS_METROPOLIS
 

@@ -56,30 +56,41 @@ __global__ __launch_bounds__(kThreads) void offspring_kernel(const int32_t *__re
     raise_flags(status, fl);
 }
 
-// One thread per (row, 4-column group); rows of D = 4 c floats.
+// Rows of D = 4 cols floats as 16-byte vectors. Each thread moves kRows
+// rows spaced a grid apart, so its ancestor loads and row gathers are
+// independent and in flight together, and every load/store instruction is
+// coalesced across the wave (consecutive lanes, consecutive rows).
+constexpr int kRows = 4;
+
 __global__ __launch_bounds__(kThreads) void copy_rows_vec4(const int32_t *__restrict__ anc,
                                                            const float4 *__restrict__ x_in,
                                                            float4 *__restrict__ x_out, int64_t P,
-                                                           int32_t cols, int cols_log2,
-                                                           int32_t *status)
+                                                           int32_t cols, int32_t *status)
 {
-    const int64_t total = P * (int64_t)cols;
-    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    const int64_t nthreads = (int64_t)gridDim.x * kThreads;
     int fl = 0;
-    for (int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x; q < total; q += stride) {
-        int64_t i, c;
-        if (cols_log2 >= 0) {
-            i = q >> cols_log2;
-            c = q & (cols - 1);
-        } else {
-            i = q / cols;
-            c = q - i * cols;
+    for (int64_t r0 = (int64_t)blockIdx.x * kThreads + threadIdx.x; r0 < P; r0 += kRows * nthreads) {
+        int32_t a[kRows];
+#pragma unroll
+        for (int k = 0; k < kRows; ++k) {
+            const int64_t r = r0 + k * nthreads;
+            a[k] = r < P ? anc[r] : 0;
         }
-        const int32_t a = anc[i];
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (a >= 0 && (int64_t)a < P) v = x_in[(int64_t)a * cols + c];
-        else fl |= kFlagBadAncestor;
-        x_out[q] = v;
+        for (int32_t c = 0; c < cols; ++c) {
+            float4 v[kRows];
+#pragma unroll
+            for (int k = 0; k < kRows; ++k) {
+                const int64_t r = r0 + k * nthreads;
+                const bool ok = a[k] >= 0 && (int64_t)a[k] < P;
+                v[k] = (r < P && ok) ? x_in[(int64_t)a[k] * cols + c] : make_float4(0.f, 0.f, 0.f, 0.f);
+                if (r < P && !ok) fl |= kFlagBadAncestor;
+            }
+#pragma unroll
+            for (int k = 0; k < kRows; ++k) {
+                const int64_t r = r0 + k * nthreads;
+                if (r < P) x_out[r * cols + c] = v[k];
+            }
+        }
     }
     raise_flags(status, fl);
 }
@@ -174,15 +185,12 @@ int launch_permute_copy(const int32_t *anc, const float *x_in, float *x_out, int
         hipLaunchKernelGGL(copy_rows_d1, dim3(grid_for((P + 3) / 4)), dim3(kThreads), 0, stream,
                            anc, x_in, x_out, P, status);
     } else if (vec_ok) {
-        const int32_t cols = D / 4;
-        int lg = -1;
-        if ((cols & (cols - 1)) == 0) {
-            lg = 0;
-            while ((1 << lg) < cols) ++lg;
-        }
-        hipLaunchKernelGGL(copy_rows_vec4, dim3(grid_for(P * cols)), dim3(kThreads), 0, stream,
-                           anc, reinterpret_cast<const float4 *>(x_in),
-                           reinterpret_cast<float4 *>(x_out), P, cols, lg, status);
+        int64_t grid = (P + kThreads * kRows - 1) / (kThreads * kRows);
+        if (grid < 1) grid = 1;
+        if (grid > 65535) grid = 65535;
+        hipLaunchKernelGGL(copy_rows_vec4, dim3((uint32_t)grid), dim3(kThreads), 0, stream, anc,
+                           reinterpret_cast<const float4 *>(x_in),
+                           reinterpret_cast<float4 *>(x_out), P, D / 4, status);
     } else {
         hipLaunchKernelGGL(copy_rows_scalar, dim3(grid_for(P * (int64_t)D)), dim3(kThreads), 0,
                            stream, anc, x_in, x_out, P, D, status);

@@ -30,9 +30,7 @@ constexpr int kAdaptiveB = 5;  // log-sum-exp plus the eq. (5) iteration count
 
 struct alignas(64) WsHeader {
     int flags;       // OR of data flags; nonzero = table invalid
-    int n_overflow;  // fill chunks beyond one per tile
     float m;         // max lw
-    float pad;
     double W;        // total weight sum exp(lw - m)
     double delta;    // W / P
     double lse;      // m + log W
@@ -41,7 +39,7 @@ struct alignas(64) WsHeader {
 };
 
 struct WsLayout {
-    size_t header, tile_max, tile_sum, tile_flags, bound, count, overflow, cumw, total;
+    size_t header, tile_max, tile_sum, tile_flags, bound, count, cumw, total;
 };
 
 __host__ __device__ inline size_t ws_align(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -58,18 +56,23 @@ __host__ __device__ inline WsLayout ws_layout(int64_t P, bool with_cumw)
     L.tile_flags = L.tile_sum + ws_align(n * sizeof(double));
     L.bound = L.tile_flags + ws_align(n * sizeof(int32_t));
     L.count = L.bound + ws_align(n * sizeof(double));
-    L.overflow = L.count + ws_align(n * sizeof(int32_t));
-    L.cumw = L.overflow + ws_align((n + 1) * sizeof(int32_t));
+    L.cumw = L.count + ws_align(n * sizeof(int32_t));
     L.total = L.cumw + (with_cumw ? ws_align((size_t)P * sizeof(double)) : 0);
     return L;
 }
 
-// Upper bound on the fill blocks beyond one per tile (launch size): tile t
-// needs ceil((n_t + 3) / kChunk) blocks for its n_t draw points.
-__host__ __device__ inline int64_t max_overflow_chunks(int64_t P)
+// Fill blocks of a stratified/systematic resampling: one per tile, plus one
+// per kChunk-wide window of draw indices for tiles that own more than fit in
+// their first window (see fill_body).
+__host__ __device__ inline int64_t num_fill_blocks(int64_t P)
 {
-    const int64_t n = num_tiles(P);
-    return (P + 3 * n + kChunk - 1) / kChunk;
+    return num_tiles(P) + (P + kChunk - 1) / kChunk;
 }
+
+// Up to this many tiles a fill block rebuilds all tile boundaries itself (in
+// LDS) instead of reading them from a separate table launch: for small
+// instances the extra launch costs more than the redundant scan, for large
+// ones (measured at 1024 tiles) the other way round.
+constexpr int64_t kFusedTableTiles = 64;
 
 }  // namespace rs

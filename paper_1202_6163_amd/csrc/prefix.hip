@@ -12,15 +12,16 @@
 // Design on MI355X.
 //  1. tile_reduce_kernel streams lw once: per 1024-weight tile the max, the
 //     sum of exp(lw - tile max) in binary64 and the data flags.
-//  2. table_kernel (one block) rescales the tile sums to the
-//     global max, scans them into tile boundaries B_t, counts for every
-//     boundary the draw points below it (stratified/systematic draws are
-//     non-decreasing, so this is a short search near B_t / (W/P)), and lays
-//     out the fill blocks: one per tile, plus one per further 2048 draws of a
-//     tile that owns more.
-//  3. fill_kernel: each block re-reads its tile of lw, rebuilds the tile's
-//     cumulative weights in LDS with a wave-level scan, and locates each of
-//     its draw points there, writing ancestors in order.
+//  2. fill_kernel: every block rescales the tile sums to the global max and
+//     scans them into the tile boundaries B_t in LDS (a few KB: the same
+//     computation in every block costs less than another dependent launch),
+//     counts the draws below its tile's two boundaries (stratified/systematic
+//     draws are non-decreasing, so this is a short search near B / (W/P)),
+//     re-reads its tile of lw, rebuilds the tile's cumulative weights in LDS
+//     with a wave-level scan and locates each of its draws there, writing
+//     ancestors in order. Blocks beyond one per tile take the draws of heavy
+//     tiles by 2048-wide windows of draw index. Above 64 tiles a one-block
+//     table launch computes boundaries and counts once instead.
 // HBM traffic is two reads of lw and one write of anc; the cumulative weights
 // are stored only on request. The multinomial draws are unsorted, so that
 // resampler stores C (launch 3m) and bisects it per draw (launch 4m).
@@ -83,15 +84,37 @@ void launch_table(int64_t P, uint64_t seed, uint32_t instance, char *w, int32_t 
     }
 }
 
-template <int KIND>
+template <int KIND, bool FUSED>
 __global__ __launch_bounds__(kTileThreads) void fill_kernel(const float *__restrict__ lw,
                                                             int32_t *__restrict__ anc, int64_t P,
                                                             uint64_t seed, uint32_t instance,
-                                                            double *cumw, char *ws_raw)
+                                                            double *cumw, char *ws_raw,
+                                                            int32_t *status)
 {
     __shared__ double Cs[kTile];
-    fill_body<KIND>(lw, anc, P, seed, instance, cumw, ws_raw, blockIdx.x, nullptr, nullptr, 0,
-                    nullptr, Cs, nullptr);
+    extern __shared__ double sh_bound[];  // FUSED: the n tile boundaries
+    fill_body<KIND, FUSED>(lw, anc, P, seed, instance, cumw, ws_raw, blockIdx.x, nullptr, nullptr,
+                           0, status, Cs, nullptr, sh_bound);
+}
+
+// Stratified/systematic: with at most kFusedTableTiles tiles the fill blocks
+// rebuild the boundaries themselves (two launches); beyond that a table
+// launch computes them once (three launches). Same values either way: both
+// run pfx::boundaries and pfx::count_below.
+template <int KIND>
+void launch_fill(const float *lw, int32_t *anc, int64_t P, uint64_t seed, uint32_t instance,
+                 double *cumw, char *w, int32_t *status, hipStream_t stream)
+{
+    const int64_t n = num_tiles(P);
+    const dim3 grid((uint32_t)num_fill_blocks(P)), tb(kTileThreads);
+    if (n <= kFusedTableTiles) {
+        hipLaunchKernelGGL((fill_kernel<KIND, true>), grid, tb, (size_t)n * sizeof(double), stream,
+                           lw, anc, P, seed, instance, cumw, w, status);
+    } else {
+        launch_table<KIND>(P, seed, instance, w, status, nullptr, stream);
+        hipLaunchKernelGGL((fill_kernel<KIND, false>), grid, tb, 0, stream, lw, anc, P, seed,
+                           instance, cumw, w, status);
+    }
 }
 
 // ------------------------------------------------------ multinomial
@@ -117,9 +140,25 @@ __global__ __launch_bounds__(kTileThreads) void cumulative_kernel(const float *_
     store_cumw(C, P, t, Cv);
 }
 
-// Launch 4m: each thread draws two points (one Philox block) and locates
-// each by bisection over the tile boundaries (staged in LDS when they fit),
-// then over the tile's cumulative weights.
+// First index in [0, len) with a[i] > x, given a[len - 1] > x: branchless
+// bisection, ceil(log2 len) steps whatever x is.
+__device__ __forceinline__ int64_t first_above(const double *a, int64_t len, double x)
+{
+    int64_t base = 0;
+    while (len > 1) {
+        const int64_t half = len >> 1;
+        if (a[base + half - 1] <= x) base += half;
+        len -= half;
+    }
+    return base;
+}
+
+// Launch 4m: each thread draws kDraws points (two per Philox block) and
+// locates them side by side (their memory round trips overlap): bisection
+// over the tile boundaries (staged in LDS when they fit), then over the
+// tile's cumulative weights in global memory.
+constexpr int kDraws = 4;
+
 __global__ __launch_bounds__(256) void multinomial_search_kernel(const double *__restrict__ C,
                                                                  int32_t *__restrict__ anc,
                                                                  int64_t P, uint64_t seed,
@@ -137,38 +176,36 @@ __global__ __launch_bounds__(256) void multinomial_search_kernel(const double *_
         bound = sh_bound;
     }
     const double W = ws.h->W;
-    const int64_t pairs = (P + 1) >> 1;
-    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < pairs;
-         p += (int64_t)gridDim.x * blockDim.x) {
+    const double capW = below(W);
+    const int64_t groups = (P + kDraws - 1) / kDraws;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < groups;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i0 = q * kDraws;
         if (flags) {
-            anc[2 * p] = (int32_t)(2 * p);
-            if (2 * p + 1 < P) anc[2 * p + 1] = (int32_t)(2 * p + 1);
+            for (int k = 0; k < kDraws; ++k)
+                if (i0 + k < P) anc[i0 + k] = (int32_t)(i0 + k);
             continue;
         }
-        const Block4 b = philox(seed, (uint32_t)p, instance, 0u, kTagMultinomial);
-        const double xs[2] = {unit53(b.r0, b.r1) * W, unit53(b.r2, b.r3) * W};
+        double x[kDraws];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int64_t i = 2 * p + h;
-            if (i >= P) break;
-            const double xw = fmin(xs[h], below(W));
-            int64_t lo = 0, hi = n - 1;  // first tile with bound > xw
-            while (lo < hi) {
-                const int64_t mid = (lo + hi) >> 1;
-                if (bound[mid] > xw) hi = mid;
-                else lo = mid + 1;
-            }
-            const int64_t t = lo;
-            const double xt = fmin(xs[h], below(bound[t]));
-            const int64_t base = t * kTile;
-            int64_t a = 0, z = min((int64_t)kTile, P - base) - 1;  // first j with C > xt
-            while (a < z) {
-                const int64_t mid = (a + z) >> 1;
-                if (C[base + mid] > xt) z = mid;
-                else a = mid + 1;
-            }
-            anc[i] = (int32_t)(base + a);
+        for (int p = 0; p < kDraws / 2; ++p) {
+            const Block4 b = philox(seed, (uint32_t)(i0 / 2 + p), instance, 0u, kTagMultinomial);
+            x[2 * p] = unit53(b.r0, b.r1) * W;
+            x[2 * p + 1] = unit53(b.r2, b.r3) * W;
         }
+        int64_t t[kDraws];
+#pragma unroll
+        for (int k = 0; k < kDraws; ++k) t[k] = first_above(bound, n, fmin(x[k], capW));
+        int64_t j[kDraws];
+#pragma unroll
+        for (int k = 0; k < kDraws; ++k) {
+            const int64_t base = t[k] * kTile;
+            j[k] = base + first_above(C + base, min((int64_t)kTile, P - base),
+                                      fmin(x[k], below(bound[t[k]])));
+        }
+#pragma unroll
+        for (int k = 0; k < kDraws; ++k)
+            if (i0 + k < P) anc[i0 + k] = (int32_t)j[k];
     }
 }
 
@@ -182,18 +219,13 @@ int launch_prefix(int kind, const float *lw, int32_t *anc, int64_t P, uint64_t s
     const int64_t n = num_tiles(P);
     char *w = static_cast<char *>(ws);
     const dim3 tb(kTileThreads);
-    const dim3 fill_grid((uint32_t)(n + max_overflow_chunks(P)));
     hipLaunchKernelGGL(tile_reduce_kernel, dim3((uint32_t)n), tb, 0, stream, lw, P, w);
     switch (kind) {
     case kStratified:
-        launch_table<kStratified>(P, seed, instance, w, status, nullptr, stream);
-        hipLaunchKernelGGL(fill_kernel<kStratified>, fill_grid, tb, 0, stream, lw, anc, P, seed,
-                           instance, cumw, w);
+        launch_fill<kStratified>(lw, anc, P, seed, instance, cumw, w, status, stream);
         break;
     case kSystematic:
-        launch_table<kSystematic>(P, seed, instance, w, status, nullptr, stream);
-        hipLaunchKernelGGL(fill_kernel<kSystematic>, fill_grid, tb, 0, stream, lw, anc, P, seed,
-                           instance, cumw, w);
+        launch_fill<kSystematic>(lw, anc, P, seed, instance, cumw, w, status, stream);
         break;
     case kMultinomial: {
         double *C = cumw ? cumw : reinterpret_cast<double *>(w + ws_layout(P, true).cumw);
@@ -201,9 +233,8 @@ int launch_prefix(int kind, const float *lw, int32_t *anc, int64_t P, uint64_t s
         hipLaunchKernelGGL(cumulative_kernel, dim3((uint32_t)n), tb, 0, stream, lw, P, C, w);
         const int lds_bounds = n <= 4096 ? 1 : 0;
         const size_t smem = lds_bounds ? (size_t)n * sizeof(double) : 0;
-        const int64_t pairs = (P + 1) >> 1;
-        int64_t grid = (pairs + 255) / 256;
-        if (grid > 8192) grid = 8192;
+        int64_t grid = ((P + kDraws - 1) / kDraws + 255) / 256;
+        if (grid > 16384) grid = 16384;
         hipLaunchKernelGGL(multinomial_search_kernel, dim3((uint32_t)grid), dim3(256), smem, stream,
                            C, anc, P, seed, instance, w, lds_bounds);
         break;

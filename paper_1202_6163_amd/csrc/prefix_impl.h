@@ -132,7 +132,6 @@ struct WsView {
     int32_t *tile_flags;
     double *bound;
     int32_t *count;
-    int32_t *overflow;
 };
 
 __device__ __forceinline__ WsView ws_view(char *ws, int64_t P)
@@ -145,7 +144,6 @@ __device__ __forceinline__ WsView ws_view(char *ws, int64_t P)
     v.tile_flags = reinterpret_cast<int32_t *>(ws + L.tile_flags);
     v.bound = reinterpret_cast<double *>(ws + L.bound);
     v.count = reinterpret_cast<int32_t *>(ws + L.count);
-    v.overflow = reinterpret_cast<int32_t *>(ws + L.overflow);
     return v;
 }
 
@@ -241,29 +239,28 @@ __device__ inline void tile_reduce_body(const float *__restrict__ lw, int64_t P,
 }
 
 // ------------------------------------------------------ phase 2: table
-// Global max, tile boundaries B_t (scaled tile sums, scanned, then made
-// non-decreasing by a running maximum), and for stratified/systematic the
-// draw counts below each boundary and the fill layout: one block per tile
-// plus one per further kChunk draws. `bound` and `count` are scratch for n
-// tiles (LDS when they fit, else the workspace arrays themselves).
-template <int KIND>
-__device__ void table_body(int64_t P, uint64_t seed, uint32_t instance, char *ws_raw,
-                           int32_t *status, double *lse_out, double *bound, int32_t *count,
-                           double eps = 0.0, uint32_t B_max = 0, uint32_t *B_used = nullptr)
+// Tile boundaries B_t of all n tiles into bound[] (LDS or the workspace):
+// global max, tile sums rescaled to it, an exclusive block scan plus a
+// per-thread running sum, then a running maximum so B never decreases. Every
+// caller (table kernel, fused fill, batched table) runs exactly this code, so
+// the boundaries are the same bits on every path. Returns the data flags
+// (then bound is unspecified) and sets *m_out, *W_out.
+struct TableSums {
+    int flags;
+    float m;
+    double W;
+};
+
+__device__ inline TableSums boundaries(const WsView &ws, int64_t P, double *bound)
 {
     __shared__ double redd[kNW];
     __shared__ float redf[kNW];
     __shared__ int redi[kNW];
-    __shared__ int64_t redl[kNW];
     __shared__ double sh_W;
-    const WsView ws = ws_view(ws_raw, P);
-    WsHeader *h = ws.h;
     const int64_t n = num_tiles(P);
     const int tid = threadIdx.x;
-    const bool staged = bound != ws.bound;
     const int64_t per = (n + kTileThreads - 1) / kTileThreads;
     const int64_t t0 = min(n, (int64_t)tid * per), t1 = min(n, t0 + per);
-
     int fl = 0;
     float m = -INFINITY;
     for (int64_t t = t0; t < t1; ++t) {
@@ -274,18 +271,7 @@ __device__ void table_body(int64_t P, uint64_t seed, uint32_t instance, char *ws
     fl = block_or(fl, redi);
     m = block_max(m, redf);
     if (!(m > -INFINITY)) fl |= kFlagAllNegInf;
-    if (fl) {
-        if (tid == 0) {
-            h->flags = fl;
-            h->n_overflow = 0;
-            h->B = 0;
-            if (B_used) *B_used = 0;
-            if (lse_out)
-                *lse_out = (fl & (kFlagNan | kFlagPosInf)) ? (double)NAN : -(double)INFINITY;
-            raise_flags(status, fl);
-        }
-        return;
-    }
+    if (fl) return TableSums{fl, m, 0.0};
     double local = 0.0;
     for (int64_t t = t0; t < t1; ++t) {
         const float mt = ws.tile_max[t];
@@ -304,13 +290,43 @@ __device__ void table_body(int64_t P, uint64_t seed, uint32_t instance, char *ws
     for (int64_t t = t0; t < t1; ++t) {
         const double b = fmax(bound[t], carry);
         bound[t] = b;
-        if (staged) ws.bound[t] = b;
         if (t == n - 1) sh_W = b;
     }
     __syncthreads();
-    const double W = sh_W;
-    const double delta = W / (double)P;
+    return TableSums{0, m, sh_W};
+}
 
+// The table launch: boundaries, and for stratified/systematic the draw
+// counts below every boundary, into the workspace. `bound` and `count` are
+// scratch for n tiles (LDS when they fit, else the workspace arrays).
+template <int KIND>
+__device__ void table_body(int64_t P, uint64_t seed, uint32_t instance, char *ws_raw,
+                           int32_t *status, double *lse_out, double *bound, int32_t *count,
+                           double eps = 0.0, uint32_t B_max = 0, uint32_t *B_used = nullptr)
+{
+    const WsView ws = ws_view(ws_raw, P);
+    WsHeader *h = ws.h;
+    const int64_t n = num_tiles(P);
+    const int tid = threadIdx.x;
+    const bool staged = bound != ws.bound;
+    const TableSums sums = boundaries(ws, P, bound);
+    if (sums.flags) {
+        if (tid == 0) {
+            h->flags = sums.flags;
+            h->B = 0;
+            if (B_used) *B_used = 0;
+            if (lse_out)
+                *lse_out = (sums.flags & (kFlagNan | kFlagPosInf)) ? (double)NAN
+                                                                   : -(double)INFINITY;
+            raise_flags(status, sums.flags);
+        }
+        return;
+    }
+    const int64_t per = (n + kTileThreads - 1) / kTileThreads;
+    const int64_t t0 = min(n, (int64_t)tid * per), t1 = min(n, t0 + per);
+    const double W = sums.W, delta = W / (double)P;
+    if (staged)
+        for (int64_t t = t0; t < t1; ++t) ws.bound[t] = bound[t];
     if (KIND == kStratified || KIND == kSystematic) {
         const double u_sys = KIND == kSystematic ? systematic_offset(seed, instance) : 0.0;
         for (int64_t t = t0; t < t1; ++t) {
@@ -319,32 +335,12 @@ __device__ void table_body(int64_t P, uint64_t seed, uint32_t instance, char *ws
             count[t] = cnt;
             if (staged) ws.count[t] = cnt;
         }
-        __syncthreads();  // the previous thread's last count is visible
-        int64_t nov = 0;
-        for (int64_t t = t0; t < t1; ++t) {
-            const int64_t lo = t > 0 ? count[t - 1] : 0, hi = count[t];
-            const int64_t span = hi - (lo & ~(int64_t)3);
-            nov += span > kChunk ? (span + kChunk - 1) / kChunk - 1 : 0;
-        }
-        int64_t tot_ov;
-        int64_t acc = block_exclusive_isum(nov, redl, &tot_ov);
-        for (int64_t t = t0; t < t1; ++t) {
-            ws.overflow[t] = (int32_t)acc;
-            const int64_t lo = t > 0 ? count[t - 1] : 0, hi = count[t];
-            const int64_t span = hi - (lo & ~(int64_t)3);
-            acc += span > kChunk ? (span + kChunk - 1) / kChunk - 1 : 0;
-        }
-        if (tid == 0) {
-            ws.overflow[n] = (int32_t)tot_ov;
-            h->n_overflow = (int32_t)tot_ov;
-            if (tot_ov > max_overflow_chunks(P)) raise_flags(status, kFlagInternal);
-        }
     }
     if (tid == 0) {
-        h->m = m;
+        h->m = sums.m;
         h->W = W;
         h->delta = delta;
-        h->lse = (double)m + log(W);
+        h->lse = (double)sums.m + log(W);
         h->flags = 0;
         if (lse_out) *lse_out = h->lse;
         if (KIND == kAdaptiveB) {
@@ -446,30 +442,59 @@ __device__ inline void copy_rows_from_lds(const int32_t *sh_anc, int64_t a0, int
 }
 
 // ------------------------------------------------------ phase 3: fill
-// Fill block g of an instance: tile g (g < n) or an extra chunk of a heavy
-// tile. Writes the block's ancestors (and, with x_in, copies their rows).
+// First tile t with B_t > x, for x < W (bisection over n non-decreasing
+// boundaries in LDS or global memory).
+__device__ __forceinline__ int64_t tile_of(const double *bound, int64_t n, double x)
+{
+    int64_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (bound[mid] > x) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+// Fill block g of an instance. Blocks g < n serve tile g's draws
+// [lo, hi) up to the next multiple of kChunk; block n + q serves the draws
+// [q kChunk, (q+1) kChunk) of the tile that owns draw q kChunk when that tile
+// started before it (a heavy tile). Together they cover every draw once.
+// With FUSED the block rebuilds the boundaries in LDS (sh_bound, n doubles)
+// and counts the draws itself; otherwise it reads the table launch's output.
+// Writes the ancestors (and, with x_in, copies their rows).
 // Cs: kTile doubles, sh_anc: kChunk ints of LDS.
-template <int KIND>
+template <int KIND, bool FUSED>
 __device__ void fill_body(const float *__restrict__ lw, int32_t *__restrict__ anc, int64_t P,
                           uint64_t seed, uint32_t instance, double *cumw, char *ws_raw, int64_t g,
                           const float *x_in, float *x_out, int32_t D, int32_t *status, double *Cs,
-                          int32_t *sh_anc)
+                          int32_t *sh_anc, double *sh_bound)
 {
+    __shared__ int64_t sh_range[4];  // tile, first draw, end draw, slot base
     const WsView ws = ws_view(ws_raw, P);
     const int64_t n = num_tiles(P);
-    int64_t t = g, c = 0;
+    const bool tile_block = g < n;
     float v[4];
-    // every read this block needs is issued up front (one memory round trip)
-    const int64_t tq = g < n ? g : n - 1;
-    load_tile4(lw, P, tq, v);
-    const int flags = ws.h->flags;
-    const int n_ov = ws.h->n_overflow;
-    const double delta = ws.h->delta;
-    const float m = ws.h->m;
-    int64_t lo = tq > 0 ? ws.count[tq - 1] : 0, hi = ws.count[tq];
-    double Blo = tq > 0 ? ws.bound[tq - 1] : 0.0, Bhi = ws.bound[tq];
-    if (flags) {  // flagged input: identity ancestors (rows copied in place order)
-        if (g < n) {
+    if (tile_block) load_tile4(lw, P, g, v);  // issued before the table reads
+
+    int flags;
+    float m;
+    double W;
+    const double *bound;
+    if (FUSED) {
+        const TableSums sums = boundaries(ws, P, sh_bound);
+        flags = sums.flags;
+        m = sums.m;
+        W = sums.W;
+        bound = sh_bound;
+        if (flags && g == 0 && threadIdx.x == 0) raise_flags(status, flags);
+    } else {
+        flags = ws.h->flags;
+        m = ws.h->m;
+        W = ws.h->W;
+        bound = ws.bound;
+    }
+    if (flags) {  // flagged input: identity ancestors and rows
+        if (tile_block) {
             for (int64_t j = g * kTile + threadIdx.x; j < min(P, (g + 1) * kTile); j += kTileThreads) {
                 anc[j] = (int32_t)j;
                 if (cumw) cumw[j] = (double)NAN;
@@ -479,30 +504,56 @@ __device__ void fill_body(const float *__restrict__ lw, int32_t *__restrict__ an
         }
         return;
     }
-    if (g >= n) {
-        const int64_t q = g - n;
-        if (q >= n_ov) return;
-        int64_t a = 0, z = n - 1;  // last t with overflow[t] <= q
-        while (a < z) {
-            const int64_t mid = (a + z + 1) >> 1;
-            if (ws.overflow[mid] <= q) a = mid;
-            else z = mid - 1;
+    const double delta = W / (double)P;
+    const double u_sys = KIND == kSystematic ? systematic_offset(seed, instance) : 0.0;
+
+    // locate the block's tile t and draw window [ob, oe), slot base a0
+    if (threadIdx.x == 0) {
+        int64_t t = g, ob = 0, oe = 0, a0 = 0;
+        if (!tile_block) {
+            const int64_t base = (g - n) * kChunk;
+            t = -1;
+            if (base < P) {
+                const double x = draw_point<KIND>(base, delta, seed, instance, u_sys);
+                t = tile_of(bound, n, fmin(x, below(W)));
+            }
+            sh_range[0] = t;
         }
-        t = a;
-        c = q - ws.overflow[t] + 1;
-        load_tile4(lw, P, t, v);
-        lo = t > 0 ? ws.count[t - 1] : 0;
-        hi = ws.count[t];
-        Blo = t > 0 ? ws.bound[t - 1] : 0.0;
-        Bhi = ws.bound[t];
+        if (t >= 0) {
+            const double Blo = t > 0 ? bound[t - 1] : 0.0, Bhi = bound[t];
+            int64_t lo, hi;
+            if (FUSED) {
+                lo = count_below<KIND>(Blo, P, W, delta, seed, instance, u_sys);
+                hi = count_below<KIND>(Bhi, P, W, delta, seed, instance, u_sys);
+            } else {
+                lo = t > 0 ? ws.count[t - 1] : 0;
+                hi = ws.count[t];
+            }
+            if (tile_block) {
+                a0 = lo & ~(int64_t)3;
+                ob = lo;
+                oe = min(hi, (lo / kChunk + 1) * kChunk);
+            } else {
+                const int64_t base = (g - n) * kChunk;
+                a0 = base;
+                ob = base > lo ? base : hi;  // the tile block covers base == lo
+                oe = min(hi, base + kChunk);
+            }
+            sh_range[0] = t;
+        }
+        sh_range[1] = ob;
+        sh_range[2] = oe;
+        sh_range[3] = a0;
     }
-    const int64_t a0 = (lo & ~(int64_t)3) + c * kChunk;
-    const int64_t ob = max(lo, a0), oe = min(hi, a0 + kChunk);
-    if (ob >= oe && !(cumw && c == 0)) return;  // nothing to write
+    __syncthreads();
+    const int64_t t = sh_range[0], ob = sh_range[1], oe = sh_range[2], a0 = sh_range[3];
+    if (t < 0 || (ob >= oe && !(cumw && tile_block))) return;  // nothing to write
+    if (!tile_block) load_tile4(lw, P, t, v);
+    const double Blo = t > 0 ? bound[t - 1] : 0.0, Bhi = bound[t];
 
     double C[4];
     tile_cumulative(v, m, Blo, Bhi, Cs, C);  // ends with a barrier
-    if (cumw && c == 0) store_cumw(cumw, P, t, C);
+    if (cumw && tile_block) store_cumw(cumw, P, t, C);
 
     const int64_t o0 = a0 + 8 * (int64_t)threadIdx.x;
     if (o0 + 8 > ob && o0 < oe) {
@@ -513,7 +564,6 @@ __device__ void fill_body(const float *__restrict__ lw, int32_t *__restrict__ an
             U[0] = unit32(b0.r0); U[1] = unit32(b0.r1); U[2] = unit32(b0.r2); U[3] = unit32(b0.r3);
             U[4] = unit32(b1.r0); U[5] = unit32(b1.r1); U[6] = unit32(b1.r2); U[7] = unit32(b1.r3);
         } else {
-            const double u_sys = systematic_offset(seed, instance);
 #pragma unroll
             for (int k = 0; k < 8; ++k) U[k] = u_sys;
         }

@@ -109,3 +109,79 @@ def test_metropolis_B_matches_oracle(L):
     assert L.lib.metropolis_B(4096, 1.0 / 4096, 1e-3) == 1
     assert L.lib.metropolis_B(1, 1.0, 1e-3) == 0
     assert L.lib.metropolis_B(100, 0.0, 1e-3) == 0
+
+
+def test_struct_layouts_match_header(L, tmp_path):
+    # the ctypes mirrors must have the C layout of include/resample.h
+    import subprocess
+    src = tmp_path / "sizes.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "resample.h"\n'
+        'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(rs_instance), '
+        'offsetof(rs_instance, P), offsetof(rs_instance, seed), sizeof(rs_batch_tuning), '
+        'sizeof(rs_batch_plan), offsetof(rs_batch_plan, smem_main), '
+        'sizeof(rs_metropolis_tuning));return 0;}\n')
+    exe = tmp_path / "sizes"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    want = [ctypes.sizeof(L.Instance), L.Instance.P.offset, L.Instance.seed.offset,
+            ctypes.sizeof(L.BatchTuning), ctypes.sizeof(L.BatchPlan), L.BatchPlan.smem_main.offset,
+            ctypes.sizeof(L.Tuning)]
+    assert got == want
+
+
+def test_batch_plan_validation_before_any_upload(L):
+    lib = L.lib
+    good = L.Instance(0x1000000, 0x2000000, None, None, None, 100, 0, L.METROPOLIS, 8, 0, 1)
+    arr = (L.Instance * 1)(good)
+    assert lib.rs_batch_plan_bytes(arr, 1, None) > 0
+    assert lib.rs_batch_workspace_bytes(arr, 1) == 0
+    bad_kind = (L.Instance * 1)(L.Instance(0x1000000, 0x2000000, None, None, None, 100, 0, 77, 8,
+                                           0, 1))
+    assert lib.rs_batch_plan_bytes(bad_kind, 1, None) == 0
+    overlap = (L.Instance * 1)(L.Instance(0x1000000, 0x1000010, None, None, None, 100, 0,
+                                          L.METROPOLIS, 8, 0, 1))
+    assert lib.rs_batch_plan_bytes(overlap, 1, None) == 0
+    copy_no_out = (L.Instance * 1)(L.Instance(0x1000000, 0x2000000, 0x3000000, None, None, 100, 4,
+                                              L.STRATIFIED, 0, 0, 1))
+    assert lib.rs_batch_plan_bytes(copy_no_out, 1, None) == 0
+    bad_tuning = L.BatchTuning(300, 8, 0, 0)
+    assert lib.rs_batch_plan_bytes(arr, 1, ctypes.byref(bad_tuning)) == 0
+    plan = L.BatchPlan()
+    # plan buffer too small / missing workspace: rejected before the upload
+    assert lib.rs_batch_plan_init(ctypes.byref(plan), arr, 1, None, ctypes.c_void_p(0x4000000), 1,
+                                  None, 0, None, None) == L.RS_EWORKSPACE
+    strat = (L.Instance * 1)(L.Instance(0x1000000, 0x2000000, None, None, None, 5000, 0,
+                                        L.STRATIFIED, 0, 0, 1))
+    need = lib.rs_batch_plan_bytes(strat, 1, None)
+    assert lib.rs_batch_workspace_bytes(strat, 1) >= lib.rs_workspace_bytes(5000, L.STRATIFIED)
+    assert lib.rs_batch_plan_init(ctypes.byref(plan), strat, 1, None, ctypes.c_void_p(0x4000000),
+                                  need, None, 0, None, None) == L.RS_EWORKSPACE
+    assert lib.resample_batch(None, None) == L.RS_EINVAL
+
+
+def test_filter_argument_errors(L):
+    lib = L.lib
+    f = ctypes.c_void_p
+    assert lib.filter_init(None, 10, 8, 1, None) == L.RS_EINVAL
+    assert lib.filter_init(f(0x1000), 10, 65, 1, None) == L.RS_EINVAL
+    assert lib.filter_propagate_weight(f(0x1000), f(0x1000), f(0x90000), 10, 4, f(0x80000),
+                                       f(0x70000), 0.1, 0.5, 1, 1, None) == L.RS_EINVAL
+    assert lib.filter_propagate_weight(f(0x1000), f(0x20000), f(0x90000), 10, 4, f(0x80000),
+                                       f(0x70000), 0.1, 0.0, 1, 1, None) == L.RS_EINVAL
+    assert lib.resample_metropolis_adaptive(f(0x1000), f(0x20000), 10, 0.0, 64, 1, 0,
+                                            f(0x90000), 1 << 20, None, None, None) == L.RS_EINVAL
+    assert lib.resample_metropolis_adaptive(f(0x1000), f(0x20000), 10, 0.01, 64, 1, 0,
+                                            f(0x90000), 8, None, None, None) == L.RS_EWORKSPACE
+
+
+def test_probe_argument_errors(L):
+    lib = L.lib
+    f = ctypes.c_void_p
+    assert lib.rs_probe_gather(None, 10, 256, 1, 1, f(0x1000), None) == L.RS_EINVAL
+    assert lib.rs_probe_gather(f(0x1000), 10, 100, 1, 1, f(0x8000), None) == L.RS_EINVAL
+    assert lib.rs_probe_gather(f(0x1000), 0, 256, 1, 1, f(0x8000), None) == L.RS_EINVAL
+    assert lib.rs_probe_philox(1, 256, 0, f(0x8000), None) == L.RS_EINVAL
+    assert lib.rs_probe_philox(1, 256, 1, None, None) == L.RS_EINVAL

@@ -353,3 +353,15 @@ def test_binding_rejects_bad_tensors(rs):
     ws = torch.zeros(8, dtype=torch.uint8, device="cuda")
     with pytest.raises(ResampleError):
         rs.resample_stratified(lw, 1, ws=ws)
+
+
+@pytest.mark.gpu
+def test_measurement_probes_run(rs):
+    w = torch.randn(4096, device="cuda")
+    out = rs.rs_probe_gather(w, 512, 2, 3)
+    torch.cuda.synchronize()
+    assert torch.isfinite(out).all()
+    o2 = rs.rs_probe_philox(512, 2, 5)
+    o3 = rs.rs_probe_philox(512, 2, 5)
+    torch.cuda.synchronize()
+    assert torch.equal(o2, o3) and int((o2 != 0).sum()) > 400
