@@ -104,8 +104,7 @@ def main():
         rs.resample_metropolis(bs["lw"], B, seed, inst, anc=bs["anc"], status=status)
         rs.permute_copy(bs["anc"], bs["x"], x_out=bs["xo"], status=status)
         for fn in (rs.resample_stratified, rs.resample_systematic):
-            fn(bs["lw"], seed, inst, anc=bs["anc"], ws=ws, status=status)
-            rs.ancestors_to_offspring(bs["anc"], off=bs["off"], status=status)
+            fn(bs["lw"], seed, inst, anc=bs["anc"], ws=ws, status=status, off=bs["off"])
             rs.permute_copy(bs["anc"], bs["x"], x_out=bs["xo"], status=status)
         rs.resample_multinomial(bs["lw"], seed, inst, anc=bs["anc"], ws=ws, status=status)
         rs.permute_copy(bs["anc"], bs["x"], x_out=bs["xo"], status=status)
@@ -116,7 +115,10 @@ def main():
         big_out = torch.empty_like(big)
         only = {"metropolis": lambda bs, k: rs.resample_metropolis(bs["lw"], B, k, 0, anc=bs["anc"]),
                 "copycal": lambda bs, k: big_out.copy_(big),
-                "stratified": lambda bs, k: rs.resample_stratified(bs["lw"], k, 0, anc=bs["anc"], ws=ws),
+                "stratified": lambda bs, k: rs.resample_stratified(bs["lw"], k, 0, anc=bs["anc"], ws=ws,
+                                                                   off=bs["off"]),
+                "multinomial": lambda bs, k: rs.resample_multinomial(bs["lw"], k, 0, anc=bs["anc"],
+                                                                     ws=ws),
                 "copy": lambda bs, k: rs.permute_copy(bs["anc"], bs["x"], x_out=bs["xo"]),
                 "step": lambda bs, k: step(bs, k, 0)}[args.only]
         for bs in sets:
@@ -151,10 +153,12 @@ def main():
     for bs in sets:  # sorted ancestors for the copy
         rs.resample_stratified(bs["lw"], 7, 0, anc=bs["anc"], ws=ws)
     copy_ms = time_calls(lambda bs, k: rs.permute_copy(bs["anc"], bs["x"], x_out=bs["xo"]))
-    strat_ms = time_calls(lambda bs, k: rs.resample_stratified(bs["lw"], k, 0, anc=bs["anc"], ws=ws))
+    strat_ms = time_calls(lambda bs, k: rs.resample_stratified(bs["lw"], k, 0, anc=bs["anc"], ws=ws,
+                                                               off=bs["off"]))
     metro_ms = time_calls(lambda bs, k: rs.resample_metropolis(bs["lw"], B, k, 0, anc=bs["anc"]))
     multi_ms = time_calls(lambda bs, k: rs.resample_multinomial(bs["lw"], k, 0, anc=bs["anc"], ws=ws))
-    syst_ms = time_calls(lambda bs, k: rs.resample_systematic(bs["lw"], k, 0, anc=bs["anc"], ws=ws))
+    syst_ms = time_calls(lambda bs, k: rs.resample_systematic(bs["lw"], k, 0, anc=bs["anc"], ws=ws,
+                                                              off=bs["off"]))
     # the copy above used sorted ancestors; the sweep reports unsorted ones too
     for bs in sets:
         rs.resample_stratified(bs["lw"], 7, 0, anc=bs["anc"], ws=ws)
@@ -173,7 +177,7 @@ def main():
                     "units_per_launch": {"chain_iterations": iters},
                     "algorithmic_per_unit": {"valu_slots": METRO_SLOTS_PER_ITER}}
     else:
-        per = {"stratified": 12, "systematic": 12, "multinomial": 24,
+        per = {"stratified": 16, "systematic": 16, "multinomial": 24,
                "permute_copy": 4 + 8 * D}[dominant]
         achieved = per * P / (means[dominant] * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -181,17 +185,17 @@ def main():
                     "avg_launch_us": means[dominant] * 1e3}
     roofline["measured_ceilings"] = ceilings(torch, rs, G, sets[0]["lw"], iters / (means["metropolis"] * 1e-3))
     copy_gbs = (4 + 8 * D) * P / (np.mean(copy_ms) * 1e-3) / 1e9
-    strat_gbs = 12 * P / (np.mean(strat_ms) * 1e-3) / 1e9
-    path_gbs = (12 + 4 + 8 * D) * P / ((np.mean(copy_ms) + np.mean(strat_ms)) * 1e-3) / 1e9
+    strat_gbs = 16 * P / (np.mean(strat_ms) * 1e-3) / 1e9
+    path_gbs = (16 + 4 + 8 * D) * P / ((np.mean(copy_ms) + np.mean(strat_ms)) * 1e-3) / 1e9
     roofline_hbm = {
         "bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "permute_copy": {"achieved": copy_gbs, "frac": copy_gbs / HBM_PEAK_GBS,
                          "bytes_per_particle": 4 + 8 * D, "avg_launch_us": np.mean(copy_ms) * 1e3},
         "stratified": {"achieved": strat_gbs, "frac": strat_gbs / HBM_PEAK_GBS,
-                       "bytes_per_particle": 12, "avg_call_us": np.mean(strat_ms) * 1e3,
-                       "launches": 2},
+                       "bytes_per_particle": 16, "avg_call_us": np.mean(strat_ms) * 1e3,
+                       "launches": 3, "outputs": "ancestors and offspring"},
         "stratified_plus_copy": {"achieved": path_gbs, "frac": path_gbs / HBM_PEAK_GBS,
-                                 "bytes_per_particle": 16 + 8 * D},
+                                 "bytes_per_particle": 20 + 8 * D},
     }
 
     out = {
@@ -204,8 +208,8 @@ def main():
         "data": "synthetic", "config": {
             "workload": "resampler sweep point P=2^20, lw ~ N(0, 1), D=4 state copy; step = "
                         "Metropolis(B=32) + stratified + systematic + multinomial, each followed "
-                        "by the state copy, offspring for stratified/systematic; cold HBM "
-                        "(rotating buffer sets)",
+                        "by the state copy, stratified/systematic writing ancestors and "
+                        "offspring in one pass; cold HBM (rotating buffer sets)",
             "P": P, "D": D, "sigma": sigma, "B": B, "buffer_sets": args.sets,
             "set_bytes": set_bytes, "parallelism": "single GPU"},
         "per_call_ms_cold": {k: float(v) for k, v in means.items()},
@@ -245,10 +249,18 @@ def ceilings(torch, rs, G, lw, metro_iter_per_s):
     gathers = threads * rounds * 8 / (gather_ms * 1e-3)
     blocks = threads * rounds * 4 / (philox_ms * 1e-3)
     bound = min(gathers, 2 * blocks)
+    # the gather rate against the size of the gathered array (L2 is 4 MB per XCD)
+    by_size = {}
+    for lg in (16, 18, 19, 20, 21, 22, 24):
+        arr = torch.zeros(1 << lg, dtype=torch.float32, device=lw.device)
+        g = G.capture(lambda arr=arr: rs.rs_probe_gather(arr, threads, rounds, 1, out=out_f))
+        G.replay_ms([g], 2)
+        ms = float(np.median(G.replay_ms([g], 6)))
+        by_size[str(4 << lg)] = threads * rounds * 8 / (ms * 1e-3)
     return {"random_gather_per_s": gathers, "philox_blocks_per_s": blocks,
             "metropolis_iter_per_s": metro_iter_per_s, "iteration_ceiling_per_s": bound,
             "frac_of_measured_ceiling": metro_iter_per_s / bound,
-            "gather_array_bytes": 4 * lw.numel()}
+            "gather_array_bytes": 4 * lw.numel(), "random_gather_per_s_by_array_bytes": by_size}
 
 
 def load_traffic(kernel):

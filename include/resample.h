@@ -120,24 +120,29 @@ int resample_metropolis_adaptive(const float *lw, int32_t *anc, int64_t P, doubl
 /*
  * Stratified resampler (Sec. 2, Fig. 1(b)): one uniform draw in each stratum
  * [i, i+1) * W / P of the cumulative weight, ancestor a_i = min{j : C_j > x_i}.
- * Ancestors come out sorted. Multi-kernel: a tile reduction, then a fused
- * scan and fill.
+ * Ancestors come out sorted. The paper gives this resampler's output as
+ * offspring counts; it writes ancestors, offspring or both in the same pass.
+ * Multi-kernel: a tile reduction, a one-block table (more than 64 tiles),
+ * then a fused scan and fill.
  *   lw     [device] float[P]    log-weights
- *   anc    [device] int32[P]    ancestors (output, non-decreasing)
+ *   anc    [device] int32[P]    ancestors (output, non-decreasing), nullable
+ *   off    [device] int32[P]    offspring o_j = #{i : a_i = j} (output), nullable;
+ *                               anc and off must not both be NULL
  *   cumw   [device] double[P]   nullable; receives the cumulative weights
  *                               C_j = sum_{k<=j} exp(lw_k - max lw)
  *   ws     [device] workspace of ws_bytes >= rs_workspace_bytes(P, RS_STRATIFIED)
  *   status [device] int32[1]    nullable; RS_FLAG_NAN / POSINF / ALL_NEGINF
+ *                               (then anc is the identity and every o_j is 1)
  */
-int resample_stratified(const float *lw, int32_t *anc, int64_t P, uint64_t seed, uint32_t instance,
-                        double *cumw, void *ws, size_t ws_bytes, int32_t *status,
-                        hipStream_t stream);
+int resample_stratified(const float *lw, int32_t *anc, int32_t *off, int64_t P, uint64_t seed,
+                        uint32_t instance, double *cumw, void *ws, size_t ws_bytes,
+                        int32_t *status, hipStream_t stream);
 
 /* Systematic resampler (Sec. 2, Fig. 1(c); Kitagawa): as stratified with one
  * shared offset for every stratum. Same arguments. */
-int resample_systematic(const float *lw, int32_t *anc, int64_t P, uint64_t seed, uint32_t instance,
-                        double *cumw, void *ws, size_t ws_bytes, int32_t *status,
-                        hipStream_t stream);
+int resample_systematic(const float *lw, int32_t *anc, int32_t *off, int64_t P, uint64_t seed,
+                        uint32_t instance, double *cumw, void *ws, size_t ws_bytes,
+                        int32_t *status, hipStream_t stream);
 
 /* Multinomial resampler (Sec. 2, Fig. 1(a)): P independent uniform draws on
  * [0, W), each located by binary search in the cumulative weights. Ancestors
@@ -145,6 +150,27 @@ int resample_systematic(const float *lw, int32_t *anc, int64_t P, uint64_t seed,
 int resample_multinomial(const float *lw, int32_t *anc, int64_t P, uint64_t seed,
                          uint32_t instance, double *cumw, void *ws, size_t ws_bytes,
                          int32_t *status, hipStream_t stream);
+
+/*
+ * Sorted-weight variant of a prefix-sum resampler (Sec. 3 compares the
+ * resamplers with the weights sorted before the prefix sum, which speeds up
+ * the multinomial bisection, and without). The particles are ordered by
+ * decreasing log-weight, equal weights by index (-0 counts as +0); the
+ * resampler `kind` (RS_STRATIFIED, RS_SYSTEMATIC or RS_MULTINOMIAL) runs on
+ * the weights in that order with the given seed and instance; anc receives
+ * the chosen particles' original indices. The sort is rocPRIM's stable
+ * descending radix sort; its library internals may issue memory fills, so
+ * this call is not meant for graph capture.
+ *   lw, anc  [device] float[P] / int32[P], not overlapping
+ *   ws       [device] workspace of ws_bytes >= rs_sorted_workspace_bytes(P, kind)
+ *   status   [device] int32[1], nullable; flagged inputs give identity ancestors
+ * Errors: RS_EINVAL, RS_EWORKSPACE (also if the sort needs more scratch than
+ * the workspace bound), RS_EHIP.
+ */
+size_t rs_sorted_workspace_bytes(int64_t P, int kind);
+int resample_sorted(int kind, const float *lw, int32_t *anc, int64_t P, uint64_t seed,
+                    uint32_t instance, void *ws, size_t ws_bytes, int32_t *status,
+                    hipStream_t stream);
 
 /*
  * Offspring counts from ancestors (Sec. 2: o_j = #{i : a_i = j}).
@@ -190,6 +216,8 @@ int rs_log_sum_exp(const float *lw, int64_t P, double *out, void *ws, size_t ws_
 typedef struct rs_instance {
     const float *lw;    /* [device] float[P] log-weights */
     int32_t *anc;       /* [device] int32[P] ancestors (output) */
+    int32_t *off;       /* [device] int32[P] offspring (output; stratified and
+                           systematic only), or NULL */
     const float *x_in;  /* [device] float[P x D] state, or NULL: no copy */
     float *x_out;       /* [device] float[P x D] copied state (output) */
     int32_t *status;    /* [device] int32[1] flags of this instance, nullable */

@@ -222,6 +222,29 @@ def multinomial(lw, seed, instance=0, want_cumw=False):
     return _prefix(_lib.oracle_multinomial, lw, seed, instance, want_cumw)
 
 
+def sorted_order(lw):
+    """Particle indices by decreasing log-weight, equal weights in index order
+    (-0 and +0 are equal). The sorted-weight variants of Sec. 3 run a
+    resampler on the weights in this order."""
+    lw = _f32(lw)
+    key = np.where(lw == 0, np.float32(0), lw).astype(np.float64)
+    return np.argsort(-key, kind="stable").astype(np.int32)
+
+
+def sorted_variant(kind, lw, seed, instance=0):
+    """Sorted-weight variant of the stratified, systematic or multinomial
+    resampler (Sec. 3: the weights are sorted before the prefix sum; the
+    ancestors are mapped back to the original particle indices). Flagged
+    inputs give identity ancestors, as the plain resamplers do."""
+    fn = {"stratified": stratified, "systematic": systematic, "multinomial": multinomial}[kind]
+    lw = _f32(lw)
+    order = sorted_order(lw)
+    a_s, st = fn(lw[order], seed, instance)
+    if st:
+        return np.arange(lw.size, dtype=np.int32), st
+    return order[a_s], st
+
+
 def ancestors_to_offspring(anc):
     anc = _i32(anc)
     off = np.empty(anc.size, dtype=np.int32)

@@ -27,7 +27,8 @@ class Tuning(ctypes.Structure):
 
 
 class Instance(ctypes.Structure):
-    _fields_ = [("lw", ctypes.c_void_p), ("anc", ctypes.c_void_p), ("x_in", ctypes.c_void_p),
+    _fields_ = [("lw", ctypes.c_void_p), ("anc", ctypes.c_void_p), ("off", ctypes.c_void_p),
+                ("x_in", ctypes.c_void_p),
                 ("x_out", ctypes.c_void_p), ("status", ctypes.c_void_p), ("P", ctypes.c_int64),
                 ("D", ctypes.c_int32), ("kind", ctypes.c_int32), ("B", ctypes.c_uint32),
                 ("instance", ctypes.c_uint32), ("seed", ctypes.c_uint64)]
@@ -71,12 +72,14 @@ def _load():
         "rs_workspace_bytes": (sz, [i64, ctypes.c_int]),
         "rs_workspace_init": (ctypes.c_int, [vp, sz, vp]),
         "resample_metropolis": (ctypes.c_int, [vp, vp, i64, u32, u64, u32, i32p, vp]),
-        "resample_stratified": (ctypes.c_int, [vp, vp, i64, u64, u32, vp, vp, sz, i32p, vp]),
+        "resample_stratified": (ctypes.c_int, [vp, vp, vp, i64, u64, u32, vp, vp, sz, i32p, vp]),
         "resample_metropolis_adaptive": (ctypes.c_int, [vp, vp, i64, ctypes.c_double, u32, u64,
                                                         u32, vp, sz, vp, i32p, vp]),
-        "resample_systematic": (ctypes.c_int, [vp, vp, i64, u64, u32, vp, vp, sz, i32p, vp]),
+        "resample_systematic": (ctypes.c_int, [vp, vp, vp, i64, u64, u32, vp, vp, sz, i32p, vp]),
         "resample_multinomial": (ctypes.c_int, [vp, vp, i64, u64, u32, vp, vp, sz, i32p, vp]),
         "ancestors_to_offspring": (ctypes.c_int, [vp, vp, i64, i32p, vp]),
+        "rs_sorted_workspace_bytes": (sz, [i64, ctypes.c_int]),
+        "resample_sorted": (ctypes.c_int, [ctypes.c_int, vp, vp, i64, u64, u32, vp, sz, i32p, vp]),
         "permute_copy": (ctypes.c_int, [vp, vp, vp, i64, ctypes.c_int32, i32p, vp]),
         "rs_log_sum_exp": (ctypes.c_int, [vp, i64, vp, vp, sz, i32p, vp]),
         "metropolis_B": (u32, [i64, ctypes.c_double, ctypes.c_double]),

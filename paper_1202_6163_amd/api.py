@@ -107,37 +107,65 @@ def resample_metropolis_adaptive(lw, seed, instance=0, eps=0.01, B_max=8192, anc
     return anc
 
 
-def _prefix(fn, kind, lw, seed, instance, anc, cumw, ws, status, stream):
+def _prefix(fn, kind, lw, seed, instance, anc, cumw, ws, status, stream, off=None,
+            with_anc=True):
     _need(lw, torch.float32, "lw")
     P = lw.numel()
-    anc = torch.empty(P, dtype=torch.int32, device=lw.device) if anc is None else anc
-    _need(anc, torch.int32, "anc", P)
+    if with_anc:
+        anc = torch.empty(P, dtype=torch.int32, device=lw.device) if anc is None else anc
+        _need(anc, torch.int32, "anc", P)
+    if off is not None:
+        _need(off, torch.int32, "off", P)
     if cumw is not None:
         _need(cumw, torch.float64, "cumw", P)
     if ws is None:
         ws = workspace(P, kind, lw.device, stream)
     _need(ws, torch.uint8, "ws")
-    check(fn(_ptr(lw), _ptr(anc), P, int(seed), int(instance), _ptr(cumw), _ptr(ws), ws.numel(),
+    head = (_ptr(lw), _ptr(anc)) if kind == MULTINOMIAL else (_ptr(lw), _ptr(anc), _ptr(off))
+    check(fn(*head, P, int(seed), int(instance), _ptr(cumw), _ptr(ws), ws.numel(),
              _status_ptr(status), _stream_handle(stream)), fn.__name__)
     return anc
 
 
 def resample_stratified(lw, seed, instance=0, anc=None, cumw=None, ws=None, status=None,
-                        stream=None):
+                        stream=None, off=None, with_anc=True):
+    """Stratified resampling; returns the ancestors (None with with_anc=False,
+    which needs off). off, if given, receives the offspring counts."""
     return _prefix(lib.resample_stratified, STRATIFIED, lw, seed, instance, anc, cumw, ws, status,
-                   stream)
+                   stream, off, with_anc)
 
 
 def resample_systematic(lw, seed, instance=0, anc=None, cumw=None, ws=None, status=None,
-                        stream=None):
+                        stream=None, off=None, with_anc=True):
+    """Systematic resampling; arguments as resample_stratified."""
     return _prefix(lib.resample_systematic, SYSTEMATIC, lw, seed, instance, anc, cumw, ws, status,
-                   stream)
+                   stream, off, with_anc)
 
 
 def resample_multinomial(lw, seed, instance=0, anc=None, cumw=None, ws=None, status=None,
                          stream=None):
     return _prefix(lib.resample_multinomial, MULTINOMIAL, lw, seed, instance, anc, cumw, ws,
                    status, stream)
+
+
+def resample_sorted(kind, lw, seed, instance=0, anc=None, ws=None, status=None, stream=None):
+    """Sorted-weight variant of resampler `kind` ("stratified", "systematic",
+    "multinomial" or the RS code); returns the ancestors (original indices).
+    Not for graph capture (see include/resample.h)."""
+    code = {"stratified": STRATIFIED, "systematic": SYSTEMATIC,
+            "multinomial": MULTINOMIAL}.get(kind, kind)
+    _need(lw, torch.float32, "lw")
+    P = lw.numel()
+    anc = torch.empty(P, dtype=torch.int32, device=lw.device) if anc is None else anc
+    _need(anc, torch.int32, "anc", P)
+    if ws is None:
+        nbytes = lib.rs_sorted_workspace_bytes(P, int(code)) if P else 0
+        ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=lw.device)
+    _need(ws, torch.uint8, "ws")
+    check(lib.resample_sorted(int(code), _ptr(lw), _ptr(anc), P, int(seed), int(instance),
+                              _ptr(ws), ws.numel(), _status_ptr(status), _stream_handle(stream)),
+          "resample_sorted")
+    return anc
 
 
 def ancestors_to_offspring(anc, off=None, status=None, stream=None):

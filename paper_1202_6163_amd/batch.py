@@ -29,7 +29,8 @@ def default_tuning():
 class Batch:
     def __init__(self, instances, tuning=None, device=None, stream=None, async_upload=False):
         """instances: dicts with lw, anc, kind ('metropolis' | 'stratified' |
-        'systematic'), seed, instance, and optionally B, x_in, x_out, status.
+        'systematic'), seed, instance, and optionally B, x_in, x_out, status,
+        off (offspring output of a stratified/systematic instance).
         With async_upload the plan goes through pinned host memory held by
         this object and the call does not wait for the device."""
         self.device = torch.device(device) if device is not None else torch.device(
@@ -52,7 +53,11 @@ class Batch:
             st = d.get("status")
             if st is not None:
                 _need(st, torch.int32, "status")
+            off = d.get("off")
+            if off is not None:
+                _need(off, torch.int32, "off", lw.numel())
             arr[k] = _lib.Instance(lw.data_ptr(), anc.data_ptr(),
+                                   off.data_ptr() if off is not None else None,
                                    x_in.data_ptr() if x_in is not None else None,
                                    x_out.data_ptr() if x_out is not None else None,
                                    st.data_ptr() if st is not None else None, lw.numel(), D,

@@ -114,11 +114,11 @@ __global__ __launch_bounds__(kThreads) void batch_main_kernel(const BatchInstanc
             const int64_t count = min((int64_t)chains_per_item, I.P - first);
             metropolis_item<UNROLL>(I, first, count, I.P <= lds_max_p ? staging : nullptr, sh_anc);
         } else if (I.kind == kStratified) {
-            fill_body<kStratified, false>(I.lw, I.anc, I.P, I.seed, I.instance, nullptr, I.ws,
+            fill_body<kStratified, false>(I.lw, I.anc, I.off, I.P, I.seed, I.instance, nullptr, I.ws,
                                           item.y, I.x_in, I.x_out, I.D, I.status, Cs, sh_anc,
                                           nullptr);
         } else {
-            fill_body<kSystematic, false>(I.lw, I.anc, I.P, I.seed, I.instance, nullptr, I.ws,
+            fill_body<kSystematic, false>(I.lw, I.anc, I.off, I.P, I.seed, I.instance, nullptr, I.ws,
                                           item.y, I.x_in, I.x_out, I.D, I.status, Cs, sh_anc,
                                           nullptr);
         }

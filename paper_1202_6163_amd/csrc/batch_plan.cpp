@@ -41,16 +41,22 @@ bool valid_instance(const rs_instance &d)
 {
     if (d.P < 0 || d.P > kMaxP) return false;
     if (d.P == 0) return true;
-    if (!d.lw || !d.anc) return false;
     if (d.kind != RS_METROPOLIS && d.kind != RS_STRATIFIED && d.kind != RS_SYSTEMATIC)
         return false;
+    // Metropolis writes ancestors; stratified/systematic ancestors and/or offspring; the
+    // state copy reads the ancestors
+    if (!d.lw || (d.kind == RS_METROPOLIS && !d.anc) || (!d.anc && !d.off)) return false;
+    if (d.off && d.kind == RS_METROPOLIS) return false;
+    if (d.x_in && !d.anc) return false;
     const size_t p = (size_t)d.P;
-    if (overlaps(d.lw, 4 * p, d.anc, 4 * p)) return false;
+    if (d.anc && overlaps(d.lw, 4 * p, d.anc, 4 * p)) return false;
+    if (d.off && (overlaps(d.lw, 4 * p, d.off, 4 * p) || (d.anc && overlaps(d.anc, 4 * p, d.off, 4 * p))))
+        return false;
     if (d.x_in) {
         if (!d.x_out || d.D < 1) return false;
         const size_t rows = p * (size_t)d.D * sizeof(float);
         if (overlaps(d.x_in, rows, d.x_out, rows) || overlaps(d.anc, 4 * p, d.x_out, rows) ||
-            overlaps(d.lw, 4 * p, d.x_out, rows))
+            overlaps(d.lw, 4 * p, d.x_out, rows) || (d.off && overlaps(d.off, 4 * p, d.x_out, rows)))
             return false;
     }
     return true;
@@ -149,6 +155,7 @@ int rs_batch_plan_init(rs_batch_plan *plan, const rs_instance *descs, int32_t n,
         rs::BatchInstance &I = insts[k];
         I.lw = d.lw;
         I.anc = d.anc;
+        I.off = d.off;
         I.x_in = d.x_in;
         I.x_out = d.x_in ? d.x_out : nullptr;
         I.status = d.status;

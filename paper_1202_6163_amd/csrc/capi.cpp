@@ -77,19 +77,28 @@ bool overlaps(const void *a, size_t abytes, const void *b, size_t bbytes)
 
 int map_rc(int rc) { return rc == 0 ? RS_OK : (rc == -1 ? RS_EINVAL : RS_EHIP); }
 
-int prefix_call(int kind, const float *lw, int32_t *anc, int64_t P, uint64_t seed,
+int prefix_call(int kind, const float *lw, int32_t *anc, int32_t *off, int64_t P, uint64_t seed,
                 uint32_t instance, double *cumw, void *ws, size_t ws_bytes, int32_t *status,
                 hipStream_t stream)
 {
     if (P == 0) return RS_OK;
-    if (!lw || !anc || !ws || P < 0 || P > kMaxP) return RS_EINVAL;
+    if (!lw || (!anc && !off) || !ws || P < 0 || P > kMaxP) return RS_EINVAL;
+    if (off && kind == rs::kMultinomial) return RS_EINVAL;
     const size_t p = (size_t)P;
-    if (overlaps(lw, 4 * p, anc, 4 * p)) return RS_EINVAL;
-    if (cumw && (overlaps(cumw, 8 * p, lw, 4 * p) || overlaps(cumw, 8 * p, anc, 4 * p)))
-        return RS_EINVAL;
+    const void *outs[3] = {anc, off, cumw};
+    const size_t out_bytes[3] = {4 * p, 4 * p, 8 * p};
+    for (int a = 0; a < 3; ++a) {
+        if (!outs[a]) continue;
+        if (overlaps(outs[a], out_bytes[a], lw, 4 * p)) return RS_EINVAL;
+        for (int b = a + 1; b < 3; ++b)
+            if (outs[b] && overlaps(outs[a], out_bytes[a], outs[b], out_bytes[b])) return RS_EINVAL;
+    }
     if (ws_bytes < rs_workspace_bytes(P, kind)) return RS_EWORKSPACE;
-    if (overlaps(ws, ws_bytes, lw, 4 * p) || overlaps(ws, ws_bytes, anc, 4 * p)) return RS_EINVAL;
-    return map_rc(rs::launch_prefix(kind, lw, anc, P, seed, instance, cumw, ws, status, stream));
+    if (overlaps(ws, ws_bytes, lw, 4 * p)) return RS_EINVAL;
+    for (int a = 0; a < 3; ++a)
+        if (outs[a] && overlaps(ws, ws_bytes, outs[a], out_bytes[a])) return RS_EINVAL;
+    return map_rc(
+        rs::launch_prefix(kind, lw, anc, off, P, seed, instance, cumw, ws, status, stream));
 }
 
 }  // namespace
@@ -141,19 +150,19 @@ int resample_metropolis(const float *lw, int32_t *anc, int64_t P, uint32_t B, ui
     return map_rc(rs::launch_metropolis(lw, anc, P, B, seed, instance, status, t, stream));
 }
 
-int resample_stratified(const float *lw, int32_t *anc, int64_t P, uint64_t seed, uint32_t instance,
-                        double *cumw, void *ws, size_t ws_bytes, int32_t *status,
-                        hipStream_t stream)
+int resample_stratified(const float *lw, int32_t *anc, int32_t *off, int64_t P, uint64_t seed,
+                        uint32_t instance, double *cumw, void *ws, size_t ws_bytes,
+                        int32_t *status, hipStream_t stream)
 {
-    return prefix_call(RS_STRATIFIED, lw, anc, P, seed, instance, cumw, ws, ws_bytes, status,
+    return prefix_call(RS_STRATIFIED, lw, anc, off, P, seed, instance, cumw, ws, ws_bytes, status,
                        stream);
 }
 
-int resample_systematic(const float *lw, int32_t *anc, int64_t P, uint64_t seed, uint32_t instance,
-                        double *cumw, void *ws, size_t ws_bytes, int32_t *status,
-                        hipStream_t stream)
+int resample_systematic(const float *lw, int32_t *anc, int32_t *off, int64_t P, uint64_t seed,
+                        uint32_t instance, double *cumw, void *ws, size_t ws_bytes,
+                        int32_t *status, hipStream_t stream)
 {
-    return prefix_call(RS_SYSTEMATIC, lw, anc, P, seed, instance, cumw, ws, ws_bytes, status,
+    return prefix_call(RS_SYSTEMATIC, lw, anc, off, P, seed, instance, cumw, ws, ws_bytes, status,
                        stream);
 }
 
@@ -161,8 +170,30 @@ int resample_multinomial(const float *lw, int32_t *anc, int64_t P, uint64_t seed
                          uint32_t instance, double *cumw, void *ws, size_t ws_bytes,
                          int32_t *status, hipStream_t stream)
 {
-    return prefix_call(RS_MULTINOMIAL, lw, anc, P, seed, instance, cumw, ws, ws_bytes, status,
-                       stream);
+    return prefix_call(RS_MULTINOMIAL, lw, anc, nullptr, P, seed, instance, cumw, ws, ws_bytes,
+                       status, stream);
+}
+
+size_t rs_sorted_workspace_bytes(int64_t P, int kind)
+{
+    if (P < 1 || (kind != RS_STRATIFIED && kind != RS_SYSTEMATIC && kind != RS_MULTINOMIAL))
+        return 0;
+    return rs::sorted_layout(P, kind).total;
+}
+
+int resample_sorted(int kind, const float *lw, int32_t *anc, int64_t P, uint64_t seed,
+                    uint32_t instance, void *ws, size_t ws_bytes, int32_t *status,
+                    hipStream_t stream)
+{
+    if (kind != RS_STRATIFIED && kind != RS_SYSTEMATIC && kind != RS_MULTINOMIAL) return RS_EINVAL;
+    if (P == 0) return RS_OK;
+    if (!lw || !anc || !ws || P < 0 || P > kMaxP) return RS_EINVAL;
+    const size_t p = (size_t)P;
+    if (overlaps(lw, 4 * p, anc, 4 * p)) return RS_EINVAL;
+    if (ws_bytes < rs_sorted_workspace_bytes(P, kind)) return RS_EWORKSPACE;
+    if (overlaps(ws, ws_bytes, lw, 4 * p) || overlaps(ws, ws_bytes, anc, 4 * p)) return RS_EINVAL;
+    const int rc = rs::launch_sorted(kind, lw, anc, P, seed, instance, ws, status, stream);
+    return rc == -2 ? RS_EWORKSPACE : map_rc(rc);
 }
 
 int ancestors_to_offspring(const int32_t *anc, int32_t *off, int64_t P, int32_t *status,

@@ -37,12 +37,21 @@ int launch_metropolis_adaptive(const float *lw, int32_t *anc, int64_t P, double 
                                uint32_t *B_used, int32_t *status, const MetropolisTuning &tune,
                                hipStream_t stream);
 
-int launch_prefix(int kind, const float *lw, int32_t *anc, int64_t P, uint64_t seed,
+int launch_prefix(int kind, const float *lw, int32_t *anc, int32_t *off, int64_t P, uint64_t seed,
                   uint32_t instance, double *cumw, void *ws, int32_t *status,
                   hipStream_t stream);
 
 int launch_log_sum_exp(const float *lw, int64_t P, double *out, void *ws, int32_t *status,
                        hipStream_t stream);
+
+// Sorted-weight variant: workspace sections (byte offsets) and the launcher.
+// Returns 0, -2 (workspace too small for the sort) or -3.
+struct SortedLayout {
+    size_t prefix, keys_in, keys_out, idx_in, perm, a_sorted, temp, temp_bytes, total;
+};
+SortedLayout sorted_layout(int64_t P, int kind);
+int launch_sorted(int kind, const float *lw, int32_t *anc, int64_t P, uint64_t seed,
+                  uint32_t instance, void *ws, int32_t *status, hipStream_t stream);
 
 // Tile reduction + table that leaves the eq. (5) iteration count (capped by
 // B_max) in the workspace header (adaptive_B_slot) and in *B_used if given.
@@ -70,6 +79,7 @@ constexpr int kMetropolisKind = 3;  // RS_METROPOLIS
 struct BatchInstance {
     const float *lw;
     int32_t *anc;
+    int32_t *off;       // nullptr: no offspring
     const float *x_in;  // nullptr: no copy
     float *x_out;
     int32_t *status;

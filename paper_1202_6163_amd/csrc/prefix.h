@@ -5,8 +5,9 @@
 // reduces every tile to (max, sum of exp(lw - max), data flags). Launch 2 (one
 // block) combines the partials into the tile boundaries B_t (the cumulative
 // weight at each tile end), the number of draw points below each boundary and
-// the fill table. Launch 3 recomputes each tile's scan on chip and writes
-// ancestors (stratified/systematic: a merge of sorted draw points with sorted
+// the owner tile of every kChunk-wide window of draws. Launch 3 recomputes
+// each tile's scan on chip and writes ancestors and offspring
+// (stratified/systematic: a merge of sorted draw points with sorted
 // cumulative weights) or the cumulative weights (multinomial, searched by a
 // fourth launch). Kernel boundaries order the phases, so no block waits on
 // another and the workspace needs no initialisation.
@@ -19,7 +20,8 @@ namespace rs {
 
 constexpr int kTile = 1024;          // weights per tile
 constexpr int kTileThreads = 256;    // threads per tile block (4 weights each)
-constexpr int kChunk = 2048;         // outputs per fill block (8 per thread)
+constexpr int kChunk = 2048;         // output slots per fill block (8 per thread)
+constexpr int kWindow = kChunk - 4;  // draws per overflow window (see fill_body)
 
 // Kinds of prefix-sum pass.
 constexpr int kStratified = 0;
@@ -39,12 +41,31 @@ struct alignas(64) WsHeader {
 };
 
 struct WsLayout {
-    size_t header, tile_max, tile_sum, tile_flags, bound, count, cumw, total;
+    size_t header, tile_max, tile_sum, tile_flags, bound, count, win, sub, cumw, total;
 };
 
 __host__ __device__ inline size_t ws_align(size_t x) { return (x + 255) & ~(size_t)255; }
 
 __host__ __device__ inline int64_t num_tiles(int64_t P) { return (P + kTile - 1) / kTile; }
+
+// kWindow-wide windows of draw indices (the unit of the fill's overflow blocks).
+__host__ __device__ inline int64_t num_windows(int64_t P) { return (P + kWindow - 1) / kWindow; }
+
+// Multinomial search: every kSubStride-th cumulative weight (the last of each
+// group of kSubStride) is kept in a compact array small enough to stage in
+// LDS (at most kSubMax doubles); the stride doubles beyond 2^20 particles.
+constexpr int64_t kSubMax = 16384;
+__host__ __device__ inline int64_t sub_stride(int64_t P)
+{
+    int64_t s = 64;
+    while ((P + s - 1) / s > kSubMax) s <<= 1;
+    return s;
+}
+__host__ __device__ inline int64_t num_sub(int64_t P)
+{
+    const int64_t s = sub_stride(P);
+    return (P + s - 1) / s;
+}
 
 __host__ __device__ inline WsLayout ws_layout(int64_t P, bool with_cumw)
 {
@@ -56,17 +77,19 @@ __host__ __device__ inline WsLayout ws_layout(int64_t P, bool with_cumw)
     L.tile_flags = L.tile_sum + ws_align(n * sizeof(double));
     L.bound = L.tile_flags + ws_align(n * sizeof(int32_t));
     L.count = L.bound + ws_align(n * sizeof(double));
-    L.cumw = L.count + ws_align(n * sizeof(int32_t));
+    L.win = L.count + ws_align(n * sizeof(int32_t));
+    L.sub = L.win + ws_align((size_t)num_windows(P) * sizeof(int32_t));
+    L.cumw = L.sub + (with_cumw ? ws_align((size_t)num_sub(P) * sizeof(double)) : 0);
     L.total = L.cumw + (with_cumw ? ws_align((size_t)P * sizeof(double)) : 0);
     return L;
 }
 
 // Fill blocks of a stratified/systematic resampling: one per tile, plus one
-// per kChunk-wide window of draw indices for tiles that own more than fit in
-// their first window (see fill_body).
+// per kWindow-wide window of draw indices for the draws of heavy tiles that
+// do not fit in their tile block (see fill_body).
 __host__ __device__ inline int64_t num_fill_blocks(int64_t P)
 {
-    return num_tiles(P) + (P + kChunk - 1) / kChunk;
+    return num_tiles(P) + num_windows(P);
 }
 
 // Up to this many tiles a fill block rebuilds all tile boundaries itself (in

@@ -22,9 +22,13 @@
 //     ancestors in order. Blocks beyond one per tile take the draws of heavy
 //     tiles by 2048-wide windows of draw index. Above 64 tiles a one-block
 //     table launch computes boundaries and counts once instead.
-// HBM traffic is two reads of lw and one write of anc; the cumulative weights
-// are stored only on request. The multinomial draws are unsorted, so that
-// resampler stores C (launch 3m) and bisects it per draw (launch 4m).
+//     With an offspring array each tile block also writes o_j for its tile's
+//     particles, counted from the sorted ancestors it holds in LDS.
+// HBM traffic is two reads of lw and one write of anc (and/or off); the
+// cumulative weights are stored only on request. The multinomial draws are
+// unsorted, so that resampler stores C (launch 3m) and searches it per draw
+// (launch 4m): every 64th C' staged in LDS, then the 64 C' of the draw's
+// group in HBM.
 //
 // Rounding: inside a tile C'_j = min(B_{t-1} + L_j, B_t), where L_j is a
 // zero-weight-aware running maximum of the tile's scan, and C'_j = B_t from
@@ -86,15 +90,17 @@ void launch_table(int64_t P, uint64_t seed, uint32_t instance, char *w, int32_t 
 
 template <int KIND, bool FUSED>
 __global__ __launch_bounds__(kTileThreads) void fill_kernel(const float *__restrict__ lw,
-                                                            int32_t *__restrict__ anc, int64_t P,
+                                                            int32_t *__restrict__ anc,
+                                                            int32_t *__restrict__ off, int64_t P,
                                                             uint64_t seed, uint32_t instance,
                                                             double *cumw, char *ws_raw,
                                                             int32_t *status)
 {
     __shared__ double Cs[kTile];
+    __shared__ int32_t sh_anc[kChunk];  // the block's ancestors, for the offspring counts
     extern __shared__ double sh_bound[];  // FUSED: the n tile boundaries
-    fill_body<KIND, FUSED>(lw, anc, P, seed, instance, cumw, ws_raw, blockIdx.x, nullptr, nullptr,
-                           0, status, Cs, nullptr, sh_bound);
+    fill_body<KIND, FUSED>(lw, anc, off, P, seed, instance, cumw, ws_raw, blockIdx.x, nullptr,
+                           nullptr, 0, status, Cs, sh_anc, sh_bound);
 }
 
 // Stratified/systematic: with at most kFusedTableTiles tiles the fill blocks
@@ -102,23 +108,25 @@ __global__ __launch_bounds__(kTileThreads) void fill_kernel(const float *__restr
 // launch computes them once (three launches). Same values either way: both
 // run pfx::boundaries and pfx::count_below.
 template <int KIND>
-void launch_fill(const float *lw, int32_t *anc, int64_t P, uint64_t seed, uint32_t instance,
-                 double *cumw, char *w, int32_t *status, hipStream_t stream)
+void launch_fill(const float *lw, int32_t *anc, int32_t *off, int64_t P, uint64_t seed,
+                 uint32_t instance, double *cumw, char *w, int32_t *status, hipStream_t stream)
 {
     const int64_t n = num_tiles(P);
     const dim3 grid((uint32_t)num_fill_blocks(P)), tb(kTileThreads);
     if (n <= kFusedTableTiles) {
         hipLaunchKernelGGL((fill_kernel<KIND, true>), grid, tb, (size_t)n * sizeof(double), stream,
-                           lw, anc, P, seed, instance, cumw, w, status);
+                           lw, anc, off, P, seed, instance, cumw, w, status);
     } else {
         launch_table<KIND>(P, seed, instance, w, status, nullptr, stream);
-        hipLaunchKernelGGL((fill_kernel<KIND, false>), grid, tb, 0, stream, lw, anc, P, seed,
+        hipLaunchKernelGGL((fill_kernel<KIND, false>), grid, tb, 0, stream, lw, anc, off, P, seed,
                            instance, cumw, w, status);
     }
 }
 
 // ------------------------------------------------------ multinomial
-// Launch 3m: one block per tile writes C' for the tile.
+// Launch 3m: one block per tile writes C' for the tile, and the last C' of
+// every kSubStride-wide group into the compact array ws.sub (the group that
+// holds P - 1 takes the C' at its padded end, which equals W like C'_{P-1}).
 __global__ __launch_bounds__(kTileThreads) void cumulative_kernel(const float *__restrict__ lw,
                                                                   int64_t P, double *C,
                                                                   char *ws_raw)
@@ -138,6 +146,12 @@ __global__ __launch_bounds__(kTileThreads) void cumulative_kernel(const float *_
     double Cv[4];
     tile_cumulative(v, ws.h->m, Blo, ws.bound[t], Cs, Cv);
     store_cumw(C, P, t, Cv);
+    const int64_t S = sub_stride(P), ns = num_sub(P);
+    const int64_t e = t * kTile + 4 * (int64_t)threadIdx.x + 3;  // this thread's last element
+    if ((e + 1) % S == 0 && e / S < ns)
+        ws.sub[e / S] = Cv[3];
+    else if (S > kTile && t == num_tiles(P) - 1 && threadIdx.x == kTileThreads - 1)
+        ws.sub[ns - 1] = Cv[3];  // last group ends past the last tile
 }
 
 // First index in [0, len) with a[i] > x, given a[len - 1] > x: branchless
@@ -153,33 +167,33 @@ __device__ __forceinline__ int64_t first_above(const double *a, int64_t len, dou
     return base;
 }
 
-// Launch 4m: each thread draws kDraws points (two per Philox block) and
+// Launch 4m: a persistent grid of 1024-thread blocks. Each block stages
+// ws.sub (the last C' of every group of S = sub_stride(P) particles; at most
+// 128 KB) in LDS; each thread draws kDraws points (two per Philox block) and
 // locates them side by side (their memory round trips overlap): bisection
-// over the tile boundaries (staged in LDS when they fit), then over the
-// tile's cumulative weights in global memory.
+// over the staged group ends, then over the group's S cumulative weights in
+// global memory (S = 64 up to 2^20 particles: six dependent reads within four
+// cache lines).
 constexpr int kDraws = 4;
+constexpr int kSearchThreads = 1024;
 
-__global__ __launch_bounds__(256) void multinomial_search_kernel(const double *__restrict__ C,
-                                                                 int32_t *__restrict__ anc,
-                                                                 int64_t P, uint64_t seed,
-                                                                 uint32_t instance, char *ws_raw,
-                                                                 int lds_bounds)
+__global__ __launch_bounds__(kSearchThreads) void multinomial_search_kernel(
+    const double *__restrict__ C, int32_t *__restrict__ anc, int64_t P, uint64_t seed,
+    uint32_t instance, char *ws_raw)
 {
-    extern __shared__ double sh_bound[];
+    extern __shared__ double sh_sub[];
     const WsView ws = ws_view(ws_raw, P);
-    const int64_t n = num_tiles(P);
+    const int64_t S = sub_stride(P), ns = num_sub(P);
     const int flags = ws.h->flags;
-    const double *bound = ws.bound;
-    if (lds_bounds) {
-        for (int64_t t = threadIdx.x; t < n; t += blockDim.x) sh_bound[t] = ws.bound[t];
-        __syncthreads();
-        bound = sh_bound;
-    }
     const double W = ws.h->W;
+    if (!flags) {
+        for (int64_t k = threadIdx.x; k < ns; k += kSearchThreads) sh_sub[k] = ws.sub[k];
+        __syncthreads();
+    }
     const double capW = below(W);
     const int64_t groups = (P + kDraws - 1) / kDraws;
-    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < groups;
-         q += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t q = blockIdx.x * (int64_t)kSearchThreads + threadIdx.x; q < groups;
+         q += (int64_t)gridDim.x * kSearchThreads) {
         const int64_t i0 = q * kDraws;
         if (flags) {
             for (int k = 0; k < kDraws; ++k)
@@ -190,29 +204,33 @@ __global__ __launch_bounds__(256) void multinomial_search_kernel(const double *_
 #pragma unroll
         for (int p = 0; p < kDraws / 2; ++p) {
             const Block4 b = philox(seed, (uint32_t)(i0 / 2 + p), instance, 0u, kTagMultinomial);
-            x[2 * p] = unit53(b.r0, b.r1) * W;
-            x[2 * p + 1] = unit53(b.r2, b.r3) * W;
+            x[2 * p] = fmin(unit53(b.r0, b.r1) * W, capW);
+            x[2 * p + 1] = fmin(unit53(b.r2, b.r3) * W, capW);
         }
-        int64_t t[kDraws];
+        int64_t gk[kDraws];
 #pragma unroll
-        for (int k = 0; k < kDraws; ++k) t[k] = first_above(bound, n, fmin(x[k], capW));
+        for (int k = 0; k < kDraws; ++k) gk[k] = first_above(sh_sub, ns, x[k]);
         int64_t j[kDraws];
 #pragma unroll
         for (int k = 0; k < kDraws; ++k) {
-            const int64_t base = t[k] * kTile;
-            j[k] = base + first_above(C + base, min((int64_t)kTile, P - base),
-                                      fmin(x[k], below(bound[t[k]])));
+            const int64_t base = gk[k] * S;
+            j[k] = base + first_above(C + base, min(S, P - base), x[k]);
         }
+        if (i0 + kDraws <= P && (((uintptr_t)(anc + i0)) & 15) == 0) {
+            *reinterpret_cast<int4 *>(anc + i0) =
+                make_int4((int32_t)j[0], (int32_t)j[1], (int32_t)j[2], (int32_t)j[3]);
+        } else {
 #pragma unroll
-        for (int k = 0; k < kDraws; ++k)
-            if (i0 + k < P) anc[i0 + k] = (int32_t)j[k];
+            for (int k = 0; k < kDraws; ++k)
+                if (i0 + k < P) anc[i0 + k] = (int32_t)j[k];
+        }
     }
 }
 
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
-int launch_prefix(int kind, const float *lw, int32_t *anc, int64_t P, uint64_t seed,
+int launch_prefix(int kind, const float *lw, int32_t *anc, int32_t *off, int64_t P, uint64_t seed,
                   uint32_t instance, double *cumw, void *ws, int32_t *status,
                   hipStream_t stream)
 {
@@ -222,21 +240,29 @@ int launch_prefix(int kind, const float *lw, int32_t *anc, int64_t P, uint64_t s
     hipLaunchKernelGGL(tile_reduce_kernel, dim3((uint32_t)n), tb, 0, stream, lw, P, w);
     switch (kind) {
     case kStratified:
-        launch_fill<kStratified>(lw, anc, P, seed, instance, cumw, w, status, stream);
+        launch_fill<kStratified>(lw, anc, off, P, seed, instance, cumw, w, status, stream);
         break;
     case kSystematic:
-        launch_fill<kSystematic>(lw, anc, P, seed, instance, cumw, w, status, stream);
+        launch_fill<kSystematic>(lw, anc, off, P, seed, instance, cumw, w, status, stream);
         break;
     case kMultinomial: {
         double *C = cumw ? cumw : reinterpret_cast<double *>(w + ws_layout(P, true).cumw);
         launch_table<kMultinomial>(P, seed, instance, w, status, nullptr, stream);
         hipLaunchKernelGGL(cumulative_kernel, dim3((uint32_t)n), tb, 0, stream, lw, P, C, w);
-        const int lds_bounds = n <= 4096 ? 1 : 0;
-        const size_t smem = lds_bounds ? (size_t)n * sizeof(double) : 0;
-        int64_t grid = ((P + kDraws - 1) / kDraws + 255) / 256;
-        if (grid > 16384) grid = 16384;
-        hipLaunchKernelGGL(multinomial_search_kernel, dim3((uint32_t)grid), dim3(256), smem, stream,
-                           C, anc, P, seed, instance, w, lds_bounds);
+        const size_t smem = (size_t)num_sub(P) * sizeof(double);
+        static size_t granted = 0;  // dynamic LDS above the default needs the attribute
+        if (smem > granted) {
+            if (hipFuncSetAttribute(reinterpret_cast<const void *>(&multinomial_search_kernel),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)smem) != hipSuccess)
+                return launch_status();
+            granted = smem;
+        }
+        const int64_t per_block = (int64_t)kDraws * kSearchThreads;
+        const int64_t need = (P + per_block - 1) / per_block;
+        const int64_t grid = need < 1 ? 1 : (need > 2048 ? 2048 : need);
+        hipLaunchKernelGGL(multinomial_search_kernel, dim3((uint32_t)grid), dim3(kSearchThreads),
+                           smem, stream, C, anc, P, seed, instance, w);
         break;
     }
     default:

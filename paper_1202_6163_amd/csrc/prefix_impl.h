@@ -132,6 +132,8 @@ struct WsView {
     int32_t *tile_flags;
     double *bound;
     int32_t *count;
+    int32_t *win;
+    double *sub;
 };
 
 __device__ __forceinline__ WsView ws_view(char *ws, int64_t P)
@@ -144,6 +146,8 @@ __device__ __forceinline__ WsView ws_view(char *ws, int64_t P)
     v.tile_flags = reinterpret_cast<int32_t *>(ws + L.tile_flags);
     v.bound = reinterpret_cast<double *>(ws + L.bound);
     v.count = reinterpret_cast<int32_t *>(ws + L.count);
+    v.win = reinterpret_cast<int32_t *>(ws + L.win);
+    v.sub = reinterpret_cast<double *>(ws + L.sub);
     return v;
 }
 
@@ -244,12 +248,19 @@ __device__ inline void tile_reduce_body(const float *__restrict__ lw, int64_t P,
 // per-thread running sum, then a running maximum so B never decreases. Every
 // caller (table kernel, fused fill, batched table) runs exactly this code, so
 // the boundaries are the same bits on every path. Returns the data flags
-// (then bound is unspecified) and sets *m_out, *W_out.
+// (then bound is unspecified), the max log-weight m and the total W.
+//
+// Each thread owns a contiguous run of tiles. Up to kRegTiles per thread
+// (n <= 1024) the run lives in registers and all its loads are in flight at
+// once; longer runs go through bound[]. Both paths perform the same
+// operations in the same order.
 struct TableSums {
     int flags;
     float m;
     double W;
 };
+
+constexpr int kRegTiles = 4;
 
 __device__ inline TableSums boundaries(const WsView &ws, int64_t P, double *bound)
 {
@@ -261,36 +272,98 @@ __device__ inline TableSums boundaries(const WsView &ws, int64_t P, double *boun
     const int tid = threadIdx.x;
     const int64_t per = (n + kTileThreads - 1) / kTileThreads;
     const int64_t t0 = min(n, (int64_t)tid * per), t1 = min(n, t0 + per);
+    const bool reg = per <= kRegTiles;  // uniform
     int fl = 0;
     float m = -INFINITY;
-    for (int64_t t = t0; t < t1; ++t) {
-        fl |= ws.tile_flags[t];
-        m = fmaxf(m, ws.tile_max[t]);
-        bound[t] = ws.tile_sum[t];
+    float mt[kRegTiles];
+    double S[kRegTiles];
+    if (reg) {
+#pragma unroll
+        for (int k = 0; k < kRegTiles; ++k) {
+            const int64_t t = t0 + k;
+            const bool in = t < t1;
+            mt[k] = in ? ws.tile_max[t] : -INFINITY;
+            S[k] = in ? ws.tile_sum[t] : 0.0;
+            fl |= in ? ws.tile_flags[t] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < kRegTiles; ++k) m = fmaxf(m, mt[k]);
+    } else {
+        for (int64_t t = t0; t < t1; ++t) {
+            fl |= ws.tile_flags[t];
+            m = fmaxf(m, ws.tile_max[t]);
+            bound[t] = ws.tile_sum[t];
+        }
     }
-    fl = block_or(fl, redi);
-    m = block_max(m, redf);
+    // flags and max in one barrier (redi/redf are next written after later barriers)
+    fl = wave_or(fl);
+    m = wave_max(m);
+    if (lane_id() == 0) {
+        redi[wave_id()] = fl;
+        redf[wave_id()] = m;
+    }
+    __syncthreads();
+    fl = 0;
+    m = -INFINITY;
+#pragma unroll
+    for (int w = 0; w < kNW; ++w) {
+        fl |= redi[w];
+        m = fmaxf(m, redf[w]);
+    }
     if (!(m > -INFINITY)) fl |= kFlagAllNegInf;
     if (fl) return TableSums{fl, m, 0.0};
     double local = 0.0;
-    for (int64_t t = t0; t < t1; ++t) {
-        const float mt = ws.tile_max[t];
-        const double S = (mt > -INFINITY) ? bound[t] * exp((double)mt - (double)m) : 0.0;
-        bound[t] = S;
-        local += S;
+    if (reg) {
+#pragma unroll
+        for (int k = 0; k < kRegTiles; ++k) {
+            if (t0 + k < t1) {
+                S[k] = (mt[k] > -INFINITY) ? S[k] * exp((double)mt[k] - (double)m) : 0.0;
+                local += S[k];
+            }
+        }
+    } else {
+        for (int64_t t = t0; t < t1; ++t) {
+            const float mtt = ws.tile_max[t];
+            const double St = (mtt > -INFINITY) ? bound[t] * exp((double)mtt - (double)m) : 0.0;
+            bound[t] = St;
+            local += St;
+        }
     }
     double run = block_exclusive_sum(local, redd);
     double tmax = 0.0;
-    for (int64_t t = t0; t < t1; ++t) {
-        run += bound[t];
-        bound[t] = run;
-        tmax = run;  // running sums grow within a thread
+    if (reg) {
+#pragma unroll
+        for (int k = 0; k < kRegTiles; ++k) {
+            if (t0 + k < t1) {
+                run += S[k];
+                S[k] = run;
+                tmax = run;  // running sums grow within a thread
+            }
+        }
+    } else {
+        for (int64_t t = t0; t < t1; ++t) {
+            run += bound[t];
+            bound[t] = run;
+            tmax = run;
+        }
     }
     const double carry = block_exclusive_max(tmax, redd);
-    for (int64_t t = t0; t < t1; ++t) {
-        const double b = fmax(bound[t], carry);
-        bound[t] = b;
-        if (t == n - 1) sh_W = b;
+    if (reg) {
+#pragma unroll
+        for (int k = 0; k < kRegTiles; ++k) {
+            const int64_t t = t0 + k;
+            if (t < t1) {
+                const double b = fmax(S[k], carry);
+                bound[t] = b;
+                if (t == n - 1) sh_W = b;
+            }
+        }
+    } else {
+        for (int64_t t = t0; t < t1; ++t) {
+            const double b = fmax(bound[t], carry);
+            bound[t] = b;
+            if (t == n - 1) sh_W = b;
+        }
     }
     __syncthreads();
     return TableSums{0, m, sh_W};
@@ -329,11 +402,39 @@ __device__ void table_body(int64_t P, uint64_t seed, uint32_t instance, char *ws
         for (int64_t t = t0; t < t1; ++t) ws.bound[t] = bound[t];
     if (KIND == kStratified || KIND == kSystematic) {
         const double u_sys = KIND == kSystematic ? systematic_offset(seed, instance) : 0.0;
+        if (per <= kRegTiles) {
+            int32_t c[kRegTiles];
+#pragma unroll
+            for (int k = 0; k < kRegTiles; ++k)
+                c[k] = t0 + k < t1 ? (int32_t)count_below<KIND>(bound[t0 + k], P, W, delta, seed,
+                                                                 instance, u_sys)
+                                   : 0;
+#pragma unroll
+            for (int k = 0; k < kRegTiles; ++k) {
+                if (t0 + k < t1) {
+                    count[t0 + k] = c[k];
+                    if (staged) ws.count[t0 + k] = c[k];
+                }
+            }
+        } else {
+            for (int64_t t = t0; t < t1; ++t) {
+                const int32_t cnt =
+                    (int32_t)count_below<KIND>(bound[t], P, W, delta, seed, instance, u_sys);
+                count[t] = cnt;
+                if (staged) ws.count[t] = cnt;
+            }
+        }
+        // overflow windows: a tile's draws beyond its block's slots, [M_t, hi_t) with
+        // M_t = (lo_t & ~3) + kChunk, go to the kWindow-wide windows they meet; the
+        // overflow parts of two tiles lie more than kWindow apart, so a window has
+        // at most one owner. Unowned windows hold -1.
+        const int64_t nw = num_windows(P);
+        for (int64_t q = tid; q < nw; q += kTileThreads) ws.win[q] = -1;
+        __syncthreads();  // also: count[t0 - 1] belongs to the previous thread
         for (int64_t t = t0; t < t1; ++t) {
-            const int32_t cnt =
-                (int32_t)count_below<KIND>(bound[t], P, W, delta, seed, instance, u_sys);
-            count[t] = cnt;
-            if (staged) ws.count[t] = cnt;
+            const int64_t lo = t > 0 ? count[t - 1] : 0, hi = count[t];
+            const int64_t M = (lo & ~(int64_t)3) + kChunk;
+            for (int64_t q = M / kWindow; M < hi && q * kWindow < hi; ++q) ws.win[q] = (int32_t)t;
         }
     }
     if (tid == 0) {
@@ -443,8 +544,8 @@ __device__ inline void copy_rows_from_lds(const int32_t *sh_anc, int64_t a0, int
 
 // ------------------------------------------------------ phase 3: fill
 // First tile t with B_t > x, for x < W (bisection over n non-decreasing
-// boundaries in LDS or global memory).
-__device__ __forceinline__ int64_t tile_of(const double *bound, int64_t n, double x)
+// boundaries in LDS).
+__device__ __forceinline__ int64_t first_bound_above(const double *bound, int64_t n, double x)
 {
     int64_t lo = 0, hi = n - 1;
     while (lo < hi) {
@@ -455,48 +556,138 @@ __device__ __forceinline__ int64_t tile_of(const double *bound, int64_t n, doubl
     return lo;
 }
 
-// Fill block g of an instance. Blocks g < n serve tile g's draws
-// [lo, hi) up to the next multiple of kChunk; block n + q serves the draws
-// [q kChunk, (q+1) kChunk) of the tile that owns draw q kChunk when that tile
-// started before it (a heavy tile). Together they cover every draw once.
+// Offspring o_j of the four particles j0 .. j0+3 of tile t, j0 = t kTile + 4 tid
+// (Sec. 2: o_j is the number of draws whose ancestor is j). When the block
+// holds every draw of the tile, [lo, hi), in sh_anc (sorted, slot r = draw
+// a0 + r), each run of equal ancestors marks its first slot and its end, and
+// o_j is the width of j's run (0 without one); otherwise (a tile whose draws
+// spill into overflow windows) o_j = N(C'_j) - N(C'_{j-1}) with N the draw
+// count below a point, C'_{-1} = B_{t-1} and N(B_{t-1}) = lo. Both give the
+// exact counts of the ancestors the fill writes. Called by the whole block.
+template <int KIND>
+__device__ void tile_offspring(int32_t *off, int64_t P, int64_t t, int64_t lo, int64_t hi,
+                               int64_t oe, int64_t a0, const int32_t *sh_anc, const double *Cs,
+                               double W, double delta, uint64_t seed, uint32_t instance,
+                               double u_sys)
+{
+    __shared__ int16_t sh_start[kTile], sh_stop[kTile];
+    const int64_t base = t * kTile;
+    const int64_t j0 = base + 4 * (int64_t)threadIdx.x;
+    int32_t o[4];
+    if (hi == oe) {  // uniform: every draw of the tile is in sh_anc
+        const int r0 = (int)(lo - a0), r1 = (int)(hi - a0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            sh_start[4 * threadIdx.x + k] = 0;
+            sh_stop[4 * threadIdx.x + k] = 0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int r = 8 * (int)threadIdx.x + k;
+            if (r >= r0 && r < r1) {
+                const int32_t a = sh_anc[r];
+                const int q = (int)(a - base);
+                if (r == r0 || sh_anc[r - 1] != a) sh_start[q] = (int16_t)r;
+                if (r == r1 - 1 || sh_anc[r + 1] != a) sh_stop[q] = (int16_t)(r + 1);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            o[k] = (int32_t)sh_stop[4 * threadIdx.x + k] - (int32_t)sh_start[4 * threadIdx.x + k];
+    } else {
+        if (j0 >= P) return;
+        int64_t prev = threadIdx.x == 0
+                           ? lo
+                           : count_below<KIND>(Cs[4 * threadIdx.x - 1], P, W, delta, seed, instance,
+                                               u_sys);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int64_t c =
+                count_below<KIND>(Cs[4 * threadIdx.x + k], P, W, delta, seed, instance, u_sys);
+            o[k] = (int32_t)(c - prev);
+            prev = c;
+        }
+    }
+    if (j0 >= P) return;
+    if (j0 + 3 < P && (((uintptr_t)off) & 15) == 0) {
+        *reinterpret_cast<int4 *>(off + j0) = make_int4(o[0], o[1], o[2], o[3]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (j0 + k < P) off[j0 + k] = o[k];
+    }
+}
+
+// Fill block g of an instance. Block g < n serves tile g's draws [lo, hi)
+// as far as its kChunk slots (base lo & ~3) reach, which is all of them
+// unless the tile is heavy (more than kChunk - 3 draws); block n + q serves
+// the draws of window [q kWindow, (q+1) kWindow) that belong to a heavy
+// tile's remainder. Together they cover every draw once.
 // With FUSED the block rebuilds the boundaries in LDS (sh_bound, n doubles)
 // and counts the draws itself; otherwise it reads the table launch's output.
-// Writes the ancestors (and, with x_in, copies their rows).
+// Writes the ancestors (anc, may be null), the offspring of the tile (off,
+// may be null; tile blocks only) and, with x_in, copies the rows.
 // Cs: kTile doubles, sh_anc: kChunk ints of LDS.
 template <int KIND, bool FUSED>
-__device__ void fill_body(const float *__restrict__ lw, int32_t *__restrict__ anc, int64_t P,
-                          uint64_t seed, uint32_t instance, double *cumw, char *ws_raw, int64_t g,
-                          const float *x_in, float *x_out, int32_t D, int32_t *status, double *Cs,
-                          int32_t *sh_anc, double *sh_bound)
+__device__ void fill_body(const float *__restrict__ lw, int32_t *__restrict__ anc,
+                          int32_t *__restrict__ off, int64_t P, uint64_t seed, uint32_t instance,
+                          double *cumw, char *ws_raw, int64_t g, const float *x_in, float *x_out,
+                          int32_t D, int32_t *status, double *Cs, int32_t *sh_anc,
+                          double *sh_bound)
 {
-    __shared__ int64_t sh_range[4];  // tile, first draw, end draw, slot base
+    __shared__ int64_t sh_range[6];  // tile, first draw, end draw, slot base, lo, hi
+    __shared__ double sh_b[2];       // B_{t-1}, B_t
     const WsView ws = ws_view(ws_raw, P);
     const int64_t n = num_tiles(P);
     const bool tile_block = g < n;
     float v[4];
     if (tile_block) load_tile4(lw, P, g, v);  // issued before the table reads
 
+    // Table path: thread 0 fetches its table entries before the flags are
+    // known (the tile index is clamped, so the speculative reads stay inside
+    // the workspace; the values are used only when the flags are clear).
+    int64_t s_t = 0, s_lo = 0, s_hi = 0;
+    double s_blo = 0.0, s_bhi = 0.0;
+    if (!FUSED && threadIdx.x == 0) {
+        const int64_t t = tile_block ? g : (int64_t)ws.win[g - n];  // -1: no owner
+        const int64_t tc = t < 0 ? 0 : (t >= n ? n - 1 : t);
+        s_t = t;
+        s_lo = tc > 0 ? ws.count[tc - 1] : 0;
+        s_hi = ws.count[tc];
+        s_blo = tc > 0 ? ws.bound[tc - 1] : 0.0;
+        s_bhi = ws.bound[tc];
+    }
+
     int flags;
     float m;
     double W;
-    const double *bound;
     if (FUSED) {
         const TableSums sums = boundaries(ws, P, sh_bound);
         flags = sums.flags;
         m = sums.m;
         W = sums.W;
-        bound = sh_bound;
-        if (flags && g == 0 && threadIdx.x == 0) raise_flags(status, flags);
+        if (g == 0 && threadIdx.x == 0) {
+            // the header as the table launch leaves it, for launches that follow
+            WsHeader *h = ws.h;
+            h->flags = flags;
+            h->m = m;
+            h->W = W;
+            h->delta = W / (double)P;
+            h->lse = flags ? (double)NAN : (double)m + log(W);
+            if (flags) raise_flags(status, flags);
+        }
     } else {
         flags = ws.h->flags;
         m = ws.h->m;
         W = ws.h->W;
-        bound = ws.bound;
     }
-    if (flags) {  // flagged input: identity ancestors and rows
+    if (flags) {  // flagged input: identity ancestors and rows, one offspring each
         if (tile_block) {
             for (int64_t j = g * kTile + threadIdx.x; j < min(P, (g + 1) * kTile); j += kTileThreads) {
-                anc[j] = (int32_t)j;
+                if (anc) anc[j] = (int32_t)j;
+                if (off) off[j] = 1;
                 if (cumw) cumw[j] = (double)NAN;
                 if (x_in)
                     for (int d = 0; d < D; ++d) x_out[j * D + d] = x_in[j * D + d];
@@ -507,54 +698,89 @@ __device__ void fill_body(const float *__restrict__ lw, int32_t *__restrict__ an
     const double delta = W / (double)P;
     const double u_sys = KIND == kSystematic ? systematic_offset(seed, instance) : 0.0;
 
-    // locate the block's tile t and draw window [ob, oe), slot base a0
+    // The block's tile t (-1: an overflow window nobody owns) and draws
+    // [lo, hi). A tile block takes the draws [lo, min(hi, a0 + kChunk)) in the
+    // slots of base a0 = lo & ~3; the rest of a heavy tile, [M, hi) with
+    // M = a0 + kChunk, goes to the overflow blocks of the windows it meets.
+    int64_t t = -1, lo = 0, hi = 0;
+    double Blo = 0.0, Bhi = 0.0;
+    if (FUSED) {
+        // The owner of overflow window q can only be the tile holding its first
+        // draw: a tile starting later in the window has its remainder beyond it.
+        __shared__ int64_t sh_t, sh_hi;
+        if (threadIdx.x == 0) {
+            int64_t tt = g;
+            if (!tile_block) {
+                const double x0 = draw_point<KIND>((g - n) * kWindow, delta, seed, instance, u_sys);
+                tt = first_bound_above(sh_bound, n, fmin(x0, below(W)));
+            }
+            sh_t = tt;
+        }
+        __syncthreads();
+        const int64_t tt = sh_t;
+        if (threadIdx.x == kWave)  // the upper count on another wave, in parallel
+            sh_hi = count_below<KIND>(sh_bound[tt], P, W, delta, seed, instance, u_sys);
+        int64_t lo_t = 0;
+        if (threadIdx.x == 0 && tt > 0)
+            lo_t = count_below<KIND>(sh_bound[tt - 1], P, W, delta, seed, instance, u_sys);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const int64_t hi_t = sh_hi;
+            const int64_t q = g - n, M = (lo_t & ~(int64_t)3) + kChunk;
+            const bool owner = tile_block || max(q * kWindow, M) < min((q + 1) * kWindow, hi_t);
+            if (owner) {
+                t = tt;
+                lo = lo_t;
+                hi = hi_t;
+                Blo = tt > 0 ? sh_bound[tt - 1] : 0.0;
+                Bhi = sh_bound[tt];
+            }
+        }
+    } else if (threadIdx.x == 0) {
+        t = s_t;
+        lo = s_lo;
+        hi = s_hi;
+        Blo = s_blo;
+        Bhi = s_bhi;
+    }
     if (threadIdx.x == 0) {
-        int64_t t = g, ob = 0, oe = 0, a0 = 0;
-        if (!tile_block) {
-            const int64_t base = (g - n) * kChunk;
-            t = -1;
-            if (base < P) {
-                const double x = draw_point<KIND>(base, delta, seed, instance, u_sys);
-                t = tile_of(bound, n, fmin(x, below(W)));
-            }
-            sh_range[0] = t;
-        }
+        int64_t ob = 0, oe = 0, a0 = 0;
         if (t >= 0) {
-            const double Blo = t > 0 ? bound[t - 1] : 0.0, Bhi = bound[t];
-            int64_t lo, hi;
-            if (FUSED) {
-                lo = count_below<KIND>(Blo, P, W, delta, seed, instance, u_sys);
-                hi = count_below<KIND>(Bhi, P, W, delta, seed, instance, u_sys);
-            } else {
-                lo = t > 0 ? ws.count[t - 1] : 0;
-                hi = ws.count[t];
-            }
+            const int64_t base = lo & ~(int64_t)3;
             if (tile_block) {
-                a0 = lo & ~(int64_t)3;
-                ob = lo;
-                oe = min(hi, (lo / kChunk + 1) * kChunk);
-            } else {
-                const int64_t base = (g - n) * kChunk;
                 a0 = base;
-                ob = base > lo ? base : hi;  // the tile block covers base == lo
+                ob = lo;
                 oe = min(hi, base + kChunk);
+            } else {
+                const int64_t q = g - n;
+                ob = max(q * kWindow, base + kChunk);
+                oe = min((q + 1) * kWindow, hi);
+                a0 = ob & ~(int64_t)3;  // ob - a0 + kWindow <= kChunk
             }
-            sh_range[0] = t;
         }
+        sh_range[0] = t;
         sh_range[1] = ob;
         sh_range[2] = oe;
         sh_range[3] = a0;
+        sh_range[4] = lo;
+        sh_range[5] = hi;
+        sh_b[0] = Blo;
+        sh_b[1] = Bhi;
     }
     __syncthreads();
-    const int64_t t = sh_range[0], ob = sh_range[1], oe = sh_range[2], a0 = sh_range[3];
-    if (t < 0 || (ob >= oe && !(cumw && tile_block))) return;  // nothing to write
+    t = sh_range[0];
+    const int64_t ob = sh_range[1], oe = sh_range[2], a0 = sh_range[3];
+    Blo = sh_b[0];
+    Bhi = sh_b[1];
+    const bool want_off = off && tile_block;
+    if (t < 0 || (ob >= oe && !(cumw && tile_block) && !want_off)) return;  // nothing to write
     if (!tile_block) load_tile4(lw, P, t, v);
-    const double Blo = t > 0 ? bound[t - 1] : 0.0, Bhi = bound[t];
 
     double C[4];
     tile_cumulative(v, m, Blo, Bhi, Cs, C);  // ends with a barrier
     if (cumw && tile_block) store_cumw(cumw, P, t, C);
 
+    const bool keep = x_in || want_off;  // ancestors needed again from LDS
     const int64_t o0 = a0 + 8 * (int64_t)threadIdx.x;
     if (o0 + 8 > ob && o0 < oe) {
         double U[8];
@@ -568,30 +794,35 @@ __device__ void fill_body(const float *__restrict__ lw, int32_t *__restrict__ an
             for (int k = 0; k < 8; ++k) U[k] = u_sys;
         }
         const double cap = below(Bhi);
+        double x[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) x[k] = fmin(((double)(o0 + k) + U[k]) * delta, cap);
         int32_t a[8];
         const int32_t tile_base = (int32_t)(t * kTile);
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const double x = ((double)(o0 + k) + U[k]) * delta;
-            a[k] = tile_base + search_tile(Cs, fmin(x, cap));
-        }
-        const bool full = (o0 >= ob) && (o0 + 8 <= oe) && ((((uintptr_t)anc) & 15) == 0);
-        if (full) {
-            int4 *dst = reinterpret_cast<int4 *>(anc + o0);
-            dst[0] = make_int4(a[0], a[1], a[2], a[3]);
-            dst[1] = make_int4(a[4], a[5], a[6], a[7]);
-        } else {
+        for (int k = 0; k < 8; ++k) a[k] = tile_base + search_tile(Cs, x[k]);
+        if (anc) {
+            const bool full = (o0 >= ob) && (o0 + 8 <= oe) && ((((uintptr_t)(anc + o0)) & 15) == 0);
+            if (full) {
+                int4 *dst = reinterpret_cast<int4 *>(anc + o0);
+                dst[0] = make_int4(a[0], a[1], a[2], a[3]);
+                dst[1] = make_int4(a[4], a[5], a[6], a[7]);
+            } else {
 #pragma unroll
-            for (int k = 0; k < 8; ++k)
-                if (o0 + k >= ob && o0 + k < oe) anc[o0 + k] = a[k];
+                for (int k = 0; k < 8; ++k)
+                    if (o0 + k >= ob && o0 + k < oe) anc[o0 + k] = a[k];
+            }
         }
-        if (x_in) {
+        if (keep) {
 #pragma unroll
             for (int k = 0; k < 8; ++k) sh_anc[8 * threadIdx.x + k] = a[k];
         }
     }
+    if (keep) __syncthreads();
+    if (want_off)
+        tile_offspring<KIND>(off, P, t, sh_range[4], sh_range[5], oe, a0, sh_anc, Cs, W, delta,
+                             seed, instance, u_sys);
     if (x_in) {
-        __syncthreads();
         int fl = 0;
         copy_rows_from_lds(sh_anc, a0, ob, oe, x_in, x_out, D, P, &fl);
         raise_flags(status, fl);

@@ -54,11 +54,27 @@ def test_argument_errors_before_launch(L):
     # overlapping input and output
     assert lib.resample_metropolis(fake, ctypes.c_void_p(0x10000004), 10, 4, 1, 0, None,
                                    None) == L.RS_EINVAL
+    third = ctypes.c_void_p(0x40000000)
     for fn in (lib.resample_stratified, lib.resample_systematic, lib.resample_multinomial):
-        assert fn(None, other, 10, 1, 0, None, ws, 1 << 20, None, None) == L.RS_EINVAL
-        assert fn(fake, other, 10, 1, 0, None, None, 1 << 20, None, None) == L.RS_EINVAL
-        assert fn(fake, other, 10, 1, 0, None, ws, 1, None, None) == L.RS_EWORKSPACE
-        assert fn(fake, fake, 10, 1, 0, None, ws, 1 << 20, None, None) == L.RS_EINVAL
+        if fn is lib.resample_multinomial:
+            call = fn
+        else:  # stratified/systematic take an offspring pointer after anc
+            def call(lw, anc, *rest, fn=fn):
+                return fn(lw, anc, None, *rest)
+        assert call(None, other, 10, 1, 0, None, ws, 1 << 20, None, None) == L.RS_EINVAL
+        assert call(fake, other, 10, 1, 0, None, None, 1 << 20, None, None) == L.RS_EINVAL
+        assert call(fake, other, 10, 1, 0, None, ws, 1, None, None) == L.RS_EWORKSPACE
+        assert call(fake, fake, 10, 1, 0, None, ws, 1 << 20, None, None) == L.RS_EINVAL
+        assert call(fake, None, 10, 1, 0, None, ws, 1 << 20, None, None) == L.RS_EINVAL
+    for fn in (lib.resample_stratified, lib.resample_systematic):
+        # offspring only is valid up to the launch; overlapping outputs are not
+        assert fn(fake, None, third, 10, 1, 0, None, ws, 1, None, None) == L.RS_EWORKSPACE
+        assert fn(fake, other, ctypes.c_void_p(0x20000008), 10, 1, 0, None, ws, 1 << 20, None,
+                  None) == L.RS_EINVAL
+        assert fn(fake, other, third, 10, 1, 0, ctypes.c_void_p(0x40000010), ws, 1 << 20, None,
+                  None) == L.RS_EINVAL
+        assert fn(fake, other, ctypes.c_void_p(0x30000000), 10, 1, 0, None, ws, 1 << 20, None,
+                  None) == L.RS_EINVAL
     assert lib.permute_copy(fake, other, other, 10, 4, None, None) == L.RS_EINVAL
     assert lib.permute_copy(fake, other, ws, 10, 0, None, None) == L.RS_EINVAL
     assert lib.ancestors_to_offspring(fake, fake, 10, None, None) == L.RS_EINVAL
@@ -69,7 +85,7 @@ def test_argument_errors_before_launch(L):
 def test_empty_resampling_is_a_no_op(L):
     lib = L.lib
     assert lib.resample_metropolis(None, None, 0, 4, 1, 0, None, None) == L.RS_OK
-    assert lib.resample_stratified(None, None, 0, 1, 0, None, None, 0, None, None) == L.RS_OK
+    assert lib.resample_stratified(None, None, None, 0, 1, 0, None, None, 0, None, None) == L.RS_OK
     assert lib.permute_copy(None, None, None, 0, 4, None, None) == L.RS_OK
     assert lib.ancestors_to_offspring(None, None, 0, None, None) == L.RS_OK
 
@@ -134,27 +150,33 @@ def test_struct_layouts_match_header(L, tmp_path):
 
 def test_batch_plan_validation_before_any_upload(L):
     lib = L.lib
-    good = L.Instance(0x1000000, 0x2000000, None, None, None, 100, 0, L.METROPOLIS, 8, 0, 1)
+
+    def inst(kind, P=100, lw=0x1000000, anc=0x2000000, off=None, x_in=None, x_out=None, D=0, B=8):
+        return L.Instance(lw=lw, anc=anc, off=off, x_in=x_in, x_out=x_out, status=None, P=P, D=D,
+                          kind=kind, B=B, instance=0, seed=1)
+
+    def plan_bytes(*insts):
+        return lib.rs_batch_plan_bytes((L.Instance * len(insts))(*insts), len(insts), None)
+
+    good = inst(L.METROPOLIS)
     arr = (L.Instance * 1)(good)
     assert lib.rs_batch_plan_bytes(arr, 1, None) > 0
     assert lib.rs_batch_workspace_bytes(arr, 1) == 0
-    bad_kind = (L.Instance * 1)(L.Instance(0x1000000, 0x2000000, None, None, None, 100, 0, 77, 8,
-                                           0, 1))
-    assert lib.rs_batch_plan_bytes(bad_kind, 1, None) == 0
-    overlap = (L.Instance * 1)(L.Instance(0x1000000, 0x1000010, None, None, None, 100, 0,
-                                          L.METROPOLIS, 8, 0, 1))
-    assert lib.rs_batch_plan_bytes(overlap, 1, None) == 0
-    copy_no_out = (L.Instance * 1)(L.Instance(0x1000000, 0x2000000, 0x3000000, None, None, 100, 4,
-                                              L.STRATIFIED, 0, 0, 1))
-    assert lib.rs_batch_plan_bytes(copy_no_out, 1, None) == 0
+    assert plan_bytes(inst(77)) == 0                                      # unknown kind
+    assert plan_bytes(inst(L.METROPOLIS, anc=0x1000010)) == 0             # lw/anc overlap
+    assert plan_bytes(inst(L.STRATIFIED, x_in=0x3000000, D=4)) == 0       # copy without x_out
+    assert plan_bytes(inst(L.METROPOLIS, anc=None)) == 0                  # Metropolis needs anc
+    assert plan_bytes(inst(L.METROPOLIS, off=0x4000000)) == 0             # and has no offspring
+    assert plan_bytes(inst(L.STRATIFIED, anc=None)) == 0                  # no output at all
+    assert plan_bytes(inst(L.STRATIFIED, anc=None, off=0x4000000)) > 0    # offspring only
+    assert plan_bytes(inst(L.SYSTEMATIC, off=0x2000100)) == 0             # anc/off overlap
     bad_tuning = L.BatchTuning(300, 8, 0, 0)
     assert lib.rs_batch_plan_bytes(arr, 1, ctypes.byref(bad_tuning)) == 0
     plan = L.BatchPlan()
     # plan buffer too small / missing workspace: rejected before the upload
     assert lib.rs_batch_plan_init(ctypes.byref(plan), arr, 1, None, ctypes.c_void_p(0x4000000), 1,
                                   None, 0, None, None) == L.RS_EWORKSPACE
-    strat = (L.Instance * 1)(L.Instance(0x1000000, 0x2000000, None, None, None, 5000, 0,
-                                        L.STRATIFIED, 0, 0, 1))
+    strat = (L.Instance * 1)(inst(L.STRATIFIED, P=5000, B=0))
     need = lib.rs_batch_plan_bytes(strat, 1, None)
     assert lib.rs_batch_workspace_bytes(strat, 1) >= lib.rs_workspace_bytes(5000, L.STRATIFIED)
     assert lib.rs_batch_plan_init(ctypes.byref(plan), strat, 1, None, ctypes.c_void_p(0x4000000),
@@ -185,3 +207,19 @@ def test_probe_argument_errors(L):
     assert lib.rs_probe_gather(f(0x1000), 0, 256, 1, 1, f(0x8000), None) == L.RS_EINVAL
     assert lib.rs_probe_philox(1, 256, 0, f(0x8000), None) == L.RS_EINVAL
     assert lib.rs_probe_philox(1, 256, 1, None, None) == L.RS_EINVAL
+
+
+def test_sorted_variant_arguments(L):
+    lib = L.lib
+    f = ctypes.c_void_p
+    assert lib.rs_sorted_workspace_bytes(1000, 3) == 0  # Metropolis has no sorted variant
+    for kind in (L.STRATIFIED, L.SYSTEMATIC, L.MULTINOMIAL):
+        b = lib.rs_sorted_workspace_bytes(1 << 16, kind)
+        assert b >= lib.rs_workspace_bytes(1 << 16, kind) + 20 * (1 << 16)
+        assert lib.resample_sorted(kind, None, None, 0, 1, 0, None, 0, None, None) == L.RS_OK
+        assert lib.resample_sorted(kind, None, f(0x1000), 10, 1, 0, f(0x9000), b, None,
+                                   None) == L.RS_EINVAL
+        assert lib.resample_sorted(kind, f(0x1000), f(0x2000), 10, 1, 0, f(0x90000), 16, None,
+                                   None) == L.RS_EWORKSPACE
+    assert lib.resample_sorted(9, f(0x1000), f(0x2000), 10, 1, 0, f(0x90000), 1 << 30, None,
+                               None) == L.RS_EINVAL

@@ -31,6 +31,8 @@ def make_instances(n, p_lo, p_hi, D, seed, with_copy=True):
         d = dict(lw=lw, anc=torch.full((Pk,), -7, dtype=torch.int32, device="cuda"),
                  kind=str(kinds[k]), B=int(rng.integers(1, 80)), seed=1000 + k,
                  instance=k, status=torch.zeros(1, dtype=torch.int32, device="cuda"))
+        if d["kind"] != "metropolis" and k % 2 == 0:
+            d["off"] = torch.full((Pk,), -7, dtype=torch.int32, device="cuda")
         if with_copy and k % 5 != 1:
             Dk = D if k % 3 else 3  # some rows of a width the vector path cannot take
             d["x_in"] = torch.from_numpy(workloads.state_rows_exact(Pk, Dk)).cuda()
@@ -41,18 +43,22 @@ def make_instances(n, p_lo, p_hi, D, seed, with_copy=True):
 
 def single(rs, d):
     lw = d["lw"]
+    off = None
     if d["kind"] == "metropolis":
         anc = rs.resample_metropolis(lw, d["B"], d["seed"], d["instance"])
     else:
-        anc = getattr(rs, f"resample_{d['kind']}")(lw, d["seed"], d["instance"])
+        off = torch.empty_like(d["anc"]) if "off" in d else None
+        anc = getattr(rs, f"resample_{d['kind']}")(lw, d["seed"], d["instance"], off=off)
     out = rs.permute_copy(anc, d["x_in"]) if "x_in" in d else None
-    return anc, out
+    return anc, out, off
 
 
 def check_batch(rs, insts):
     for k, d in enumerate(insts):
-        anc, out = single(rs, d)
+        anc, out, off = single(rs, d)
         assert torch.equal(d["anc"], anc), f"instance {k} ({d['kind']}, P={d['lw'].numel()})"
+        if off is not None:
+            assert torch.equal(d["off"], off), f"offspring of instance {k}"
         if out is not None:
             assert torch.equal(d["x_out"].view(torch.int32), out.view(torch.int32)), k
         assert int(d["status"].item()) == 0

@@ -161,6 +161,18 @@ def test_metropolis_deterministic(rs):
 
 # ----------------------------------------------------------------- prefix resamplers
 PREFIX = ["stratified", "systematic", "multinomial"]
+SORTED = ["stratified", "systematic"]  # resamplers that also write offspring
+
+
+def offspring_of(anc):
+    off, st = oracle.ancestors_to_offspring(np.asarray(anc, dtype=np.int32))
+    assert st == 0
+    return off
+
+
+def check_offspring(off_g, anc_g):
+    """The resampler's own offspring counts are exactly the counts of its ancestors."""
+    assert np.array_equal(np.asarray(off_g), offspring_of(anc_g))
 SIZES = [1, 2, 3, 1023, 1024, 1025, 4097, 100003, 1 << 16]
 
 
@@ -184,6 +196,17 @@ def test_prefix_parity(rs, kind, P, sigma):
     # the same call without cumw gives the same ancestors
     anc2 = host(getattr(rs, f"resample_{kind}")(g, seed, inst))
     assert np.array_equal(anc2, anc_g)
+    if kind in SORTED:
+        # offspring in the same pass (Sec. 2: these resamplers' native output),
+        # with and without the ancestors
+        fn = getattr(rs, f"resample_{kind}")
+        off = torch.full((P,), -1, dtype=torch.int32, device="cuda")
+        anc3 = host(fn(g, seed, inst, off=off))
+        assert np.array_equal(anc3, anc_g)
+        check_offspring(host(off), anc_g)
+        off2 = torch.full((P,), -1, dtype=torch.int32, device="cuda")
+        assert fn(g, seed, inst, off=off2, with_anc=False) is None
+        assert torch.equal(off, off2)
 
 
 @pytest.mark.parametrize("kind", PREFIX)
@@ -195,15 +218,35 @@ def test_prefix_full_size(rs, kind, sigma):
     say(kind, "P=2^20 sigma", sigma)
     anc_o, _, C_o = ORACLE_FN[kind](lw, seed, inst, want_cumw=True)
     C = torch.empty(P, dtype=torch.float64, device="cuda")
-    anc_g = host(getattr(rs, f"resample_{kind}")(dev(lw), seed, inst, cumw=C))
+    off = torch.full((P,), -1, dtype=torch.int32, device="cuda") if kind in SORTED else None
+    kw = {"off": off} if off is not None else {}
+    anc_g = host(getattr(rs, f"resample_{kind}")(dev(lw), seed, inst, cumw=C, **kw))
     worst = check_cumw(host(C), C_o)
     n = explained_mismatches(kind, anc_g, anc_o, C_o, seed, inst)
     say(f"  cumw worst rel {worst:.2e}, boundary mismatches {n}")
     if kind != "multinomial":
         assert np.all(np.diff(anc_g) >= 0)
+        check_offspring(host(off), anc_g)
 
 
-@pytest.mark.parametrize("kind", ["stratified", "systematic"])
+@pytest.mark.parametrize("kind", SORTED)
+def test_prefix_table_in_global_memory(rs, kind):
+    # more than 4096 tiles: the table launch keeps boundaries and counts in
+    # the workspace instead of LDS
+    P = 5_000_000
+    seed, inst = 6, 2
+    lw = workloads.normal_logweights(P, 1.0, seed)
+    say(kind, "P=5e6 (table in global memory)")
+    anc_o, _, C_o = ORACLE_FN[kind](lw, seed, inst, want_cumw=True)
+    C = torch.empty(P, dtype=torch.float64, device="cuda")
+    off = torch.full((P,), -1, dtype=torch.int32, device="cuda")
+    anc_g = host(getattr(rs, f"resample_{kind}")(dev(lw), seed, inst, cumw=C, off=off))
+    check_cumw(host(C), C_o)
+    explained_mismatches(kind, anc_g, anc_o, C_o, seed, inst)
+    check_offspring(host(off), anc_g)
+
+
+@pytest.mark.parametrize("kind", SORTED)
 def test_prefix_heavy_particle_overflow_chunks(rs, kind):
     # one particle carries almost all weight: its tile owns ~P outputs and is
     # split over many fill blocks
@@ -214,10 +257,14 @@ def test_prefix_heavy_particle_overflow_chunks(rs, kind):
     anc_o, _, C_o = ORACLE_FN[kind](lw, 2, 1, want_cumw=True)
     C = torch.empty(P, dtype=torch.float64, device="cuda")
     st = torch.zeros(1, dtype=torch.int32, device="cuda")
-    anc_g = host(getattr(rs, f"resample_{kind}")(dev(lw), 2, 1, cumw=C, status=st))
+    off = torch.full((P,), -1, dtype=torch.int32, device="cuda")
+    anc_g = host(getattr(rs, f"resample_{kind}")(dev(lw), 2, 1, cumw=C, status=st, off=off))
     assert int(host(st)[0]) == 0
     check_cumw(host(C), C_o)
     explained_mismatches(kind, anc_g, anc_o, C_o, 2, 1)
+    # the heavy tile's offspring come from draw counts, not from one block's ancestors
+    check_offspring(host(off), anc_g)
+    assert int(host(off)[123457]) > P // 2
 
 
 @pytest.mark.parametrize("kind", PREFIX)
@@ -238,10 +285,15 @@ def test_prefix_edge_weights(rs, kind):
     lw[-7:] = -np.inf
     anc_o, _, C_o = ORACLE_FN[kind](lw, 3, 0, want_cumw=True)
     C = torch.empty(lw.size, dtype=torch.float64, device="cuda")
-    anc_g = host(fn(dev(lw), 3, 0, cumw=C))
+    kw = {}
+    if kind in SORTED:
+        kw["off"] = torch.full((lw.size,), -1, dtype=torch.int32, device="cuda")
+    anc_g = host(fn(dev(lw), 3, 0, cumw=C, **kw))
     check_cumw(host(C), C_o)
     explained_mismatches(kind, anc_g, anc_o, C_o, 3, 0)
     assert np.all(np.isfinite(lw[anc_g])), "a zero-weight particle was selected"
+    if kw:
+        check_offspring(host(kw["off"]), anc_g)
     # a single finite weight takes every draw
     one = np.full(3000, -np.inf, dtype=np.float32)
     one[2999] = 0.25
@@ -255,9 +307,14 @@ def test_prefix_flags(rs, kind):
         lw = np.zeros(2500, dtype=np.float32)
         lw[1700] = bad
         st = torch.zeros(1, dtype=torch.int32, device="cuda")
-        anc = host(fn(dev(lw), 1, 0, status=st))
+        kw = {}
+        if kind in SORTED:
+            kw["off"] = torch.full((2500,), -1, dtype=torch.int32, device="cuda")
+        anc = host(fn(dev(lw), 1, 0, status=st, **kw))
         assert int(host(st)[0]) == flag
         assert np.array_equal(anc, np.arange(2500))
+        if kw:
+            assert np.all(host(kw["off"]) == 1)
     lw = np.full(2500, -np.inf, dtype=np.float32)
     st = torch.zeros(1, dtype=torch.int32, device="cuda")
     anc = host(fn(dev(lw), 1, 0, status=st))
@@ -365,3 +422,41 @@ def test_measurement_probes_run(rs):
     o3 = rs.rs_probe_philox(512, 2, 5)
     torch.cuda.synchronize()
     assert torch.equal(o2, o3) and int((o2 != 0).sum()) > 400
+
+
+# ----------------------------------------------------------------- sorted-weight variants
+@pytest.mark.parametrize("kind", PREFIX)
+@pytest.mark.parametrize("P", [1, 5, 1000, 5000, 100003, 1 << 16])
+def test_sorted_variant_parity(rs, kind, P):
+    seed, inst = P % 13 + 2, 1
+    lw = workloads.normal_logweights(P, 1.5, seed)
+    order = oracle.sorted_order(lw)
+    inv = np.empty(P, dtype=np.int64)
+    inv[order] = np.arange(P)
+    anc_os, st, C_o = ORACLE_FN[kind](lw[order], seed, inst, want_cumw=True)
+    assert st == 0
+    st_g = torch.zeros(1, dtype=torch.int32, device="cuda")
+    anc_g = host(rs.resample_sorted(kind, dev(lw), seed, inst, status=st_g))
+    assert int(host(st_g)[0]) == 0
+    # compare in the sorted order, where the draws and boundaries live
+    n = explained_mismatches(kind, inv[anc_g], anc_os, C_o, seed, inst)
+    if n:
+        say(f"sorted {kind} P={P}: {n} boundary mismatches (explained)")
+    want, _ = oracle.sorted_variant(kind, lw, seed, inst)
+    assert np.count_nonzero(anc_g != want) == n
+
+
+@pytest.mark.parametrize("kind", PREFIX)
+def test_sorted_variant_ties_and_flags(rs, kind):
+    eq = np.full(3000, 0.5, dtype=np.float32)  # ties keep index order: same as unsorted
+    assert np.array_equal(host(rs.resample_sorted(kind, dev(eq), 3, 0)),
+                          oracle.sorted_variant(kind, eq, 3, 0)[0])
+    signed = np.zeros(2000, dtype=np.float32)
+    signed[::2] = -0.0  # -0 and +0 are equal weights
+    assert np.array_equal(host(rs.resample_sorted(kind, dev(signed), 4, 0)),
+                          oracle.sorted_variant(kind, signed, 4, 0)[0])
+    bad = np.zeros(2000, dtype=np.float32)
+    bad[77] = np.nan
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    anc = host(rs.resample_sorted(kind, dev(bad), 1, 0, status=st))
+    assert int(host(st)[0]) == rs.FLAG_NAN and np.array_equal(anc, np.arange(2000))
