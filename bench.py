@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-filter", action="store_true")
+    ap.add_argument("--no-dirichlet", action="store_true")
+    ap.add_argument("--dirichlet-R", type=int, default=50)
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="seconds of Poisson arrivals at 2000 req/s (0: skip; the full run is 60)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -220,6 +222,8 @@ def main():
         out["sweep"] = sweep(torch, rs, workloads, args)
     if not args.no_batch:
         out["batched"] = batched(torch, rs, workloads, args)
+    if not args.no_dirichlet:
+        out["dirichlet"] = dirichlet(torch, rs, workloads, args)
     if not args.no_filter:
         out["filter"] = filter_run(torch, workloads, args)
     if args.serve_seconds > 0:
@@ -366,6 +370,66 @@ def sweep(torch, rs, workloads, args):
                              "(eps = 0.01, rounded up to the swept B grid) is faster than "
                              "stratified at p99; null: never")
     return res
+
+
+def dirichlet(torch, rs, workloads, args):
+    """Sec. 3's own experiment: Dirichlet(alpha) weights, P = 256 .. 65536,
+    alpha in {10, 1, .1, .01}; accuracy metric sum (o/P - w/W)^2 averaged over
+    R resamplings and per-call time for multinomial, stratified, systematic,
+    Metropolis at eq. (5)'s B (eps = 0.01, capped at 4096) and the
+    sorted-weight multinomial and systematic. Per-call times are eager calls
+    (events around R back-to-back calls, host dispatch included), since the
+    sort inside the sorted variants is not graph-capturable."""
+    dev = torch.device("cuda", 0)
+    R = args.dirichlet_R
+    out = {"note": "eager per-call time (host dispatch included); error averaged over R "
+                   "resamplings with different seeds", "R": R, "points": []}
+    for P in (256, 1024, 4096, 16384, 65536):
+        anc = torch.empty(P, dtype=torch.int32, device=dev)
+        off = torch.empty(P, dtype=torch.int32, device=dev)
+        ws = rs.workspace(P, rs.MULTINOMIAL, dev)
+        ws_sorted = torch.empty(max(rs.lib.rs_sorted_workspace_bytes(P, rs.MULTINOMIAL),
+                                    rs.lib.rs_sorted_workspace_bytes(P, rs.SYSTEMATIC)),
+                                dtype=torch.uint8, device=dev)
+        for alpha in (10.0, 1.0, 0.1, 0.01):
+            lw_h = workloads.dirichlet_logweights(P, alpha, 7)
+            lw = torch.from_numpy(lw_h).to(dev)
+            p = torch.exp(lw.double() - lw.max().double())
+            p = p / p.sum()
+            B = min(rs.metropolis_B(P, float(p.max()), 1e-2), 4096)
+            calls = {
+                "multinomial": lambda k: rs.resample_multinomial(lw, k, 0, anc=anc, ws=ws),
+                "stratified": lambda k: rs.resample_stratified(lw, k, 0, anc=anc, ws=ws),
+                "systematic": lambda k: rs.resample_systematic(lw, k, 0, anc=anc, ws=ws),
+                "metropolis_eq5": lambda k: rs.resample_metropolis(lw, B, k, 0, anc=anc),
+                "multinomial_sorted": lambda k: rs.resample_sorted("multinomial", lw, k, 0,
+                                                                   anc=anc, ws=ws_sorted),
+                "systematic_sorted": lambda k: rs.resample_sorted("systematic", lw, k, 0,
+                                                                  anc=anc, ws=ws_sorted),
+            }
+            point = {"P": P, "alpha": alpha, "ess_frac": float(1.0 / (p * p).sum()) / P,
+                     "B_eq5": B, "resamplers": {}}
+            for name, call in calls.items():
+                errs = []
+                for k in range(R):
+                    call(500 + k)
+                    rs.ancestors_to_offspring(anc, off=off)
+                    errs.append(((off.double() / P - p) ** 2).sum())
+                err = float(torch.stack(errs).mean())
+                for k in range(3):
+                    call(k)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for k in range(R):
+                    call(900 + k)
+                e1.record()
+                torch.cuda.synchronize()
+                point["resamplers"][name] = {"error": err, "us_per_call": e0.elapsed_time(e1) * 1e3 / R}
+            out["points"].append(point)
+            print(f"dirichlet P={P} alpha={alpha}: " + ", ".join(
+                f"{k} {v['us_per_call']:.1f}us" for k, v in point["resamplers"].items()),
+                file=sys.stderr, flush=True)
+    return out
 
 
 def batched(torch, rs, workloads, args):
