@@ -102,7 +102,8 @@ def main():
     def step(bs, seed, inst):
         # Each resampler in the paper's output form (Sec. 2: stratified and
         # systematic give offspring, multinomial and Metropolis ancestors),
-        # then the ancestor-indexed state copy.
+        # then the ancestor-indexed state copy. (The fused resample_and_copy
+        # measures no faster here; its times are reported beside.)
         rs.resample_metropolis(bs["lw"], B, seed, inst, anc=bs["anc"], status=status)
         rs.permute_copy(bs["anc"], bs["x"], x_out=bs["xo"], status=status)
         for fn in (rs.resample_stratified, rs.resample_systematic):
@@ -167,6 +168,13 @@ def main():
     means = {"metropolis": np.mean(metro_ms), "stratified": np.mean(strat_ms),
              "systematic": np.mean(syst_ms), "multinomial": np.mean(multi_ms),
              "permute_copy": np.mean(copy_ms)}
+    fused_means = {}
+    for kind in ("metropolis", "stratified", "systematic", "multinomial"):
+        fused_means[kind] = float(np.mean(time_calls(
+            lambda bs, k, kind=kind: rs.resample_and_copy(
+                kind, bs["lw"], bs["x"], k, 0, B=B, anc=bs["anc"],
+                off=bs["off"] if kind in ("stratified", "systematic") else None, x_out=bs["xo"],
+                ws=None if kind == "metropolis" else ws))))
     dominant = max(means, key=means.get)
     iters = float(P) * B
     traffic = load_traffic(dominant)
@@ -215,6 +223,7 @@ def main():
             "P": P, "D": D, "sigma": sigma, "B": B, "buffer_sets": args.sets,
             "set_bytes": set_bytes, "parallelism": "single GPU"},
         "per_call_ms_cold": {k: float(v) for k, v in means.items()},
+        "per_call_ms_cold_with_fused_copy": fused_means,
         "roofline": roofline, "roofline_hbm": roofline_hbm,
         "device": torch.cuda.get_device_name(0),
     }

@@ -152,6 +152,29 @@ int resample_multinomial(const float *lw, int32_t *anc, int64_t P, uint64_t seed
                          int32_t *status, hipStream_t stream);
 
 /*
+ * One resampling step with the state copy fused into the resampler's own
+ * launches: the ancestors (and, for stratified/systematic, the offspring)
+ * are exactly those of resample_metropolis / resample_stratified /
+ * resample_systematic / resample_multinomial with the same arguments, and
+ * x_out[i, :] = x_in[a_i, :] bit for bit, as permute_copy would write them
+ * (Sec. 1: the selected particles are carried to the next time step). The
+ * copy rides on the resampler's last kernel, where the ancestors are still
+ * in registers or LDS, so they are not read back from HBM.
+ *   kind   RS_METROPOLIS (B iterations), RS_STRATIFIED, RS_SYSTEMATIC or
+ *          RS_MULTINOMIAL
+ *   anc    [device] int32[P] ancestors (output, required)
+ *   off    [device] int32[P] offspring (stratified/systematic only), nullable
+ *   x_in   [device] float[P x D] row-major state, x_out the same shape (output);
+ *          D >= 1; outputs overlap neither each other nor lw / x_in
+ *   ws     [device] workspace of ws_bytes >= rs_workspace_bytes(P, kind);
+ *          unused (may be NULL) for RS_METROPOLIS
+ * Errors: RS_EINVAL, RS_EWORKSPACE, RS_EHIP. Graph-capturable.
+ */
+int resample_and_copy(int kind, const float *lw, int32_t *anc, int32_t *off, int64_t P, uint32_t B,
+                      uint64_t seed, uint32_t instance, const float *x_in, float *x_out,
+                      int32_t D, void *ws, size_t ws_bytes, int32_t *status, hipStream_t stream);
+
+/*
  * Sorted-weight variant of a prefix-sum resampler (Sec. 3 compares the
  * resamplers with the weights sorted before the prefix sum, which speeds up
  * the multinomial bisection, and without). The particles are ordered by

@@ -148,6 +148,38 @@ def resample_multinomial(lw, seed, instance=0, anc=None, cumw=None, ws=None, sta
                    status, stream)
 
 
+def resample_and_copy(kind, lw, x_in, seed, instance=0, B=0, anc=None, off=None, x_out=None,
+                      ws=None, status=None, stream=None):
+    """Resampler `kind` ("metropolis" with B, "stratified", "systematic",
+    "multinomial") with the state copy fused in; returns (anc, x_out)."""
+    code = {"metropolis": METROPOLIS, "stratified": STRATIFIED, "systematic": SYSTEMATIC,
+            "multinomial": MULTINOMIAL}.get(kind, kind)
+    _need(lw, torch.float32, "lw")
+    _need(x_in, torch.float32, "x_in")
+    P = lw.numel()
+    if P == 0:
+        return (torch.empty(0, dtype=torch.int32, device=lw.device) if anc is None else anc,
+                torch.empty_like(x_in) if x_out is None else x_out)
+    if x_in.numel() % P:
+        raise ValueError("x_in must hold P rows")
+    D = x_in.numel() // P
+    anc = torch.empty(P, dtype=torch.int32, device=lw.device) if anc is None else anc
+    _need(anc, torch.int32, "anc", P)
+    if off is not None:
+        _need(off, torch.int32, "off", P)
+    x_out = torch.empty_like(x_in) if x_out is None else x_out
+    _need(x_out, torch.float32, "x_out", x_in.numel())
+    if code != METROPOLIS and ws is None:
+        ws = workspace(P, code, lw.device, stream)
+    if ws is not None:
+        _need(ws, torch.uint8, "ws")
+    check(lib.resample_and_copy(int(code), _ptr(lw), _ptr(anc), _ptr(off), P, int(B), int(seed),
+                                int(instance), _ptr(x_in), _ptr(x_out), D, _ptr(ws),
+                                0 if ws is None else ws.numel(), _status_ptr(status),
+                                _stream_handle(stream)), "resample_and_copy")
+    return anc, x_out
+
+
 def resample_sorted(kind, lw, seed, instance=0, anc=None, ws=None, status=None, stream=None):
     """Sorted-weight variant of resampler `kind` ("stratified", "systematic",
     "multinomial" or the RS code); returns the ancestors (original indices).

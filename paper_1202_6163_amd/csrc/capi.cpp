@@ -174,6 +174,44 @@ int resample_multinomial(const float *lw, int32_t *anc, int64_t P, uint64_t seed
                        status, stream);
 }
 
+int resample_and_copy(int kind, const float *lw, int32_t *anc, int32_t *off, int64_t P, uint32_t B,
+                      uint64_t seed, uint32_t instance, const float *x_in, float *x_out,
+                      int32_t D, void *ws, size_t ws_bytes, int32_t *status, hipStream_t stream)
+{
+    const bool prefix = kind == RS_STRATIFIED || kind == RS_SYSTEMATIC || kind == RS_MULTINOMIAL;
+    if (!prefix && kind != RS_METROPOLIS) return RS_EINVAL;
+    if (P == 0) return RS_OK;
+    if (!lw || !anc || !x_in || !x_out || D < 1 || P < 0 || P > kMaxP) return RS_EINVAL;
+    if (off && kind != RS_STRATIFIED && kind != RS_SYSTEMATIC) return RS_EINVAL;
+    const size_t p = (size_t)P, rows = p * (size_t)D * sizeof(float);
+    if ((size_t)D > ((size_t)1 << 40) / p) return RS_EINVAL;
+    // written: anc, off, x_out; read: lw, x_in
+    const void *outs[3] = {anc, off, x_out};
+    const size_t out_bytes[3] = {4 * p, 4 * p, rows};
+    for (int a = 0; a < 3; ++a) {
+        if (!outs[a]) continue;
+        if (overlaps(outs[a], out_bytes[a], lw, 4 * p) || overlaps(outs[a], out_bytes[a], x_in, rows))
+            return RS_EINVAL;
+        for (int b = a + 1; b < 3; ++b)
+            if (outs[b] && overlaps(outs[a], out_bytes[a], outs[b], out_bytes[b])) return RS_EINVAL;
+    }
+    rs::Rows r;
+    r.x_in = x_in;
+    r.x_out = x_out;
+    r.D = D;
+    if (kind == RS_METROPOLIS) {
+        const rs::MetropolisTuning t = current_tuning();
+        return map_rc(rs::launch_metropolis(lw, anc, P, B, seed, instance, status, t, stream, r));
+    }
+    if (!ws) return RS_EINVAL;
+    if (ws_bytes < rs_workspace_bytes(P, kind)) return RS_EWORKSPACE;
+    if (overlaps(ws, ws_bytes, lw, 4 * p) || overlaps(ws, ws_bytes, x_in, rows)) return RS_EINVAL;
+    for (int a = 0; a < 3; ++a)
+        if (outs[a] && overlaps(ws, ws_bytes, outs[a], out_bytes[a])) return RS_EINVAL;
+    return map_rc(rs::launch_prefix(kind, lw, anc, off, P, seed, instance, nullptr, ws, status,
+                                    stream, r));
+}
+
 size_t rs_sorted_workspace_bytes(int64_t P, int kind)
 {
     if (P < 1 || (kind != RS_STRATIFIED && kind != RS_SYSTEMATIC && kind != RS_MULTINOMIAL))

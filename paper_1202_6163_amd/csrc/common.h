@@ -7,6 +7,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include "launch.h"
 #include <stdint.h>
 
 namespace rs {
@@ -140,6 +142,21 @@ __device__ __forceinline__ double below(double b)
 __device__ __forceinline__ void raise_flags(int32_t *status, int flags)
 {
     if (flags && status) atomicOr(status, flags);
+}
+
+// Row dst of x_out from row src of x_in, elements first, first + step, ...
+// (16-byte vectors when the rows allow).
+__device__ __forceinline__ void copy_row(const Rows &r, int64_t dst, int64_t src, int first,
+                                         int step)
+{
+    const int D = r.D;
+    if ((D & 3) == 0 && ((((uintptr_t)r.x_in) | ((uintptr_t)r.x_out)) & 15) == 0) {
+        const float4 *in = reinterpret_cast<const float4 *>(r.x_in) + src * (D / 4);
+        float4 *out = reinterpret_cast<float4 *>(r.x_out) + dst * (D / 4);
+        for (int c = first; c < D / 4; c += step) out[c] = in[c];
+    } else {
+        for (int c = first; c < D; c += step) r.x_out[dst * D + c] = r.x_in[src * D + c];
+    }
 }
 
 }  // namespace rs

@@ -13,6 +13,14 @@ namespace rs {
 int launch_status();
 int record_hip_error(hipError_t e);
 
+// Particle state rows to copy with the ancestors (x_out[i, :] = x_in[a_i, :]),
+// D binary32 values per row; x_in == nullptr: no copy.
+struct Rows {
+    const float *x_in = nullptr;
+    float *x_out = nullptr;
+    int32_t D = 0;
+};
+
 struct MetropolisTuning {
     int32_t block;
     int32_t unroll;
@@ -22,7 +30,7 @@ struct MetropolisTuning {
 
 int launch_metropolis(const float *lw, int32_t *anc, int64_t P, uint32_t B, uint64_t seed,
                       uint32_t instance, int32_t *status, const MetropolisTuning &tune,
-                      hipStream_t stream);
+                      hipStream_t stream, const Rows &rows = Rows());
 
 int launch_log_u_table(float *approx, float *exact, hipStream_t stream);
 
@@ -30,7 +38,8 @@ int launch_log_u_table(float *approx, float *exact, hipStream_t stream);
 // launches before it on the stream computed it.
 int launch_metropolis_dev_B(const float *lw, int32_t *anc, int64_t P, uint32_t B,
                             const uint32_t *B_dev, uint64_t seed, uint32_t instance,
-                            int32_t *status, const MetropolisTuning &tune, hipStream_t stream);
+                            int32_t *status, const MetropolisTuning &tune, hipStream_t stream,
+                            const Rows &rows = Rows());
 
 int launch_metropolis_adaptive(const float *lw, int32_t *anc, int64_t P, double eps,
                                uint32_t B_max, uint64_t seed, uint32_t instance, void *ws,
@@ -39,7 +48,7 @@ int launch_metropolis_adaptive(const float *lw, int32_t *anc, int64_t P, double 
 
 int launch_prefix(int kind, const float *lw, int32_t *anc, int32_t *off, int64_t P, uint64_t seed,
                   uint32_t instance, double *cumw, void *ws, int32_t *status,
-                  hipStream_t stream);
+                  hipStream_t stream, const Rows &rows = Rows());
 
 int launch_log_sum_exp(const float *lw, int64_t P, double *out, void *ws, int32_t *status,
                        hipStream_t stream);

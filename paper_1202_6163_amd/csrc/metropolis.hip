@@ -41,7 +41,8 @@ __global__ __launch_bounds__(1024) void metropolis_kernel(const float *__restric
                                                           int32_t *__restrict__ anc, uint32_t P,
                                                           uint32_t B, uint64_t seed,
                                                           uint32_t instance, int lpc_log2,
-                                                          int32_t *status, const uint32_t *B_dev)
+                                                          int32_t *status, const uint32_t *B_dev,
+                                                          Rows rows)
 {
     static_assert(UNROLL % 2 == 0, "one Philox block feeds two iterations");
     if (B_dev) B = min(B, *B_dev);  // iteration count computed on the device
@@ -65,7 +66,9 @@ __global__ __launch_bounds__(1024) void metropolis_kernel(const float *__restric
         const uint32_t g = (uint32_t)(gt & (G - 1));
         if (g == 0) raise_flags(status, weight_flags(w[i]));
         if (G == 1) {
-            anc[i] = (int32_t)chain<UNROLL>(w, P, B, seed, instance, i);
+            const uint32_t a = chain<UNROLL>(w, P, B, seed, instance, i);
+            anc[i] = (int32_t)a;
+            if (rows.x_in) copy_row(rows, i, a, 0, 1);
             continue;
         }
         uint32_t k = i;
@@ -91,13 +94,14 @@ __global__ __launch_bounds__(1024) void metropolis_kernel(const float *__restric
             }
         }
         if (g == 0) anc[i] = (int32_t)k;
+        if (rows.x_in) copy_row(rows, i, k, (int)g, (int)G);  // the group shares the row
     }
 }
 
 template <int UNROLL, bool STAGE>
 int launch_variant(const float *lw, int32_t *anc, uint32_t P, uint32_t B, uint64_t seed,
                    uint32_t instance, int lpc_log2, int block, int32_t *status,
-                   const uint32_t *B_dev, hipStream_t stream)
+                   const uint32_t *B_dev, const Rows &rows, hipStream_t stream)
 {
     const uint64_t threads = (uint64_t)P << lpc_log2;
     uint64_t grid = (threads + block - 1) / block;
@@ -115,7 +119,7 @@ int launch_variant(const float *lw, int32_t *anc, uint32_t P, uint32_t B, uint64
         }
     }
     hipLaunchKernelGGL((metropolis_kernel<UNROLL, STAGE>), dim3((uint32_t)grid), dim3(block),
-                       smem, stream, lw, anc, P, B, seed, instance, lpc_log2, status, B_dev);
+                       smem, stream, lw, anc, P, B, seed, instance, lpc_log2, status, B_dev, rows);
     return launch_status();
 }
 
@@ -151,7 +155,8 @@ int launch_log_u_table(float *approx, float *exact, hipStream_t stream)
 
 int launch_metropolis_dev_B(const float *lw, int32_t *anc, int64_t P, uint32_t B,
                             const uint32_t *B_dev, uint64_t seed, uint32_t instance,
-                            int32_t *status, const MetropolisTuning &tune, hipStream_t stream)
+                            int32_t *status, const MetropolisTuning &tune, hipStream_t stream,
+                            const Rows &rows)
 {
     const uint32_t p = (uint32_t)P;
     int lg = 0;
@@ -168,9 +173,9 @@ int launch_metropolis_dev_B(const float *lw, int32_t *anc, int64_t P, uint32_t B
 #define RS_METRO_CASE(U)                                                                       \
     case U:                                                                                    \
         return stage ? launch_variant<U, true>(lw, anc, p, B, seed, instance, lg, blk, status, \
-                                               B_dev, stream)                                  \
+                                               B_dev, rows, stream)                            \
                      : launch_variant<U, false>(lw, anc, p, B, seed, instance, lg, blk,        \
-                                                status, B_dev, stream);
+                                                status, B_dev, rows, stream);
     switch (tune.unroll) {
         RS_METRO_CASE(2)
         RS_METRO_CASE(4)
@@ -184,9 +189,10 @@ int launch_metropolis_dev_B(const float *lw, int32_t *anc, int64_t P, uint32_t B
 
 int launch_metropolis(const float *lw, int32_t *anc, int64_t P, uint32_t B, uint64_t seed,
                       uint32_t instance, int32_t *status, const MetropolisTuning &tune,
-                      hipStream_t stream)
+                      hipStream_t stream, const Rows &rows)
 {
-    return launch_metropolis_dev_B(lw, anc, P, B, nullptr, seed, instance, status, tune, stream);
+    return launch_metropolis_dev_B(lw, anc, P, B, nullptr, seed, instance, status, tune, stream,
+                                   rows);
 }
 
 int launch_metropolis_adaptive(const float *lw, int32_t *anc, int64_t P, double eps,

@@ -94,13 +94,13 @@ __global__ __launch_bounds__(kTileThreads) void fill_kernel(const float *__restr
                                                             int32_t *__restrict__ off, int64_t P,
                                                             uint64_t seed, uint32_t instance,
                                                             double *cumw, char *ws_raw,
-                                                            int32_t *status)
+                                                            int32_t *status, Rows rows)
 {
     __shared__ double Cs[kTile];
-    __shared__ int32_t sh_anc[kChunk];  // the block's ancestors, for the offspring counts
+    __shared__ int32_t sh_anc[kChunk];  // the block's ancestors (offspring counts, row copy)
     extern __shared__ double sh_bound[];  // FUSED: the n tile boundaries
-    fill_body<KIND, FUSED>(lw, anc, off, P, seed, instance, cumw, ws_raw, blockIdx.x, nullptr,
-                           nullptr, 0, status, Cs, sh_anc, sh_bound);
+    fill_body<KIND, FUSED>(lw, anc, off, P, seed, instance, cumw, ws_raw, blockIdx.x, rows.x_in,
+                           rows.x_out, rows.D, status, Cs, sh_anc, sh_bound);
 }
 
 // Stratified/systematic: with at most kFusedTableTiles tiles the fill blocks
@@ -109,17 +109,18 @@ __global__ __launch_bounds__(kTileThreads) void fill_kernel(const float *__restr
 // run pfx::boundaries and pfx::count_below.
 template <int KIND>
 void launch_fill(const float *lw, int32_t *anc, int32_t *off, int64_t P, uint64_t seed,
-                 uint32_t instance, double *cumw, char *w, int32_t *status, hipStream_t stream)
+                 uint32_t instance, double *cumw, char *w, int32_t *status, hipStream_t stream,
+                 const Rows &rows)
 {
     const int64_t n = num_tiles(P);
     const dim3 grid((uint32_t)num_fill_blocks(P)), tb(kTileThreads);
     if (n <= kFusedTableTiles) {
         hipLaunchKernelGGL((fill_kernel<KIND, true>), grid, tb, (size_t)n * sizeof(double), stream,
-                           lw, anc, off, P, seed, instance, cumw, w, status);
+                           lw, anc, off, P, seed, instance, cumw, w, status, rows);
     } else {
         launch_table<KIND>(P, seed, instance, w, status, nullptr, stream);
         hipLaunchKernelGGL((fill_kernel<KIND, false>), grid, tb, 0, stream, lw, anc, off, P, seed,
-                           instance, cumw, w, status);
+                           instance, cumw, w, status, rows);
     }
 }
 
@@ -179,7 +180,7 @@ constexpr int kSearchThreads = 1024;
 
 __global__ __launch_bounds__(kSearchThreads) void multinomial_search_kernel(
     const double *__restrict__ C, int32_t *__restrict__ anc, int64_t P, uint64_t seed,
-    uint32_t instance, char *ws_raw)
+    uint32_t instance, char *ws_raw, Rows rows)
 {
     extern __shared__ double sh_sub[];
     const WsView ws = ws_view(ws_raw, P);
@@ -196,8 +197,12 @@ __global__ __launch_bounds__(kSearchThreads) void multinomial_search_kernel(
          q += (int64_t)gridDim.x * kSearchThreads) {
         const int64_t i0 = q * kDraws;
         if (flags) {
-            for (int k = 0; k < kDraws; ++k)
-                if (i0 + k < P) anc[i0 + k] = (int32_t)(i0 + k);
+            for (int k = 0; k < kDraws; ++k) {
+                if (i0 + k < P) {
+                    anc[i0 + k] = (int32_t)(i0 + k);
+                    if (rows.x_in) copy_row(rows, i0 + k, i0 + k, 0, 1);
+                }
+            }
             continue;
         }
         double x[kDraws];
@@ -224,6 +229,11 @@ __global__ __launch_bounds__(kSearchThreads) void multinomial_search_kernel(
             for (int k = 0; k < kDraws; ++k)
                 if (i0 + k < P) anc[i0 + k] = (int32_t)j[k];
         }
+        if (rows.x_in) {
+#pragma unroll
+            for (int k = 0; k < kDraws; ++k)
+                if (i0 + k < P) copy_row(rows, i0 + k, j[k], 0, 1);
+        }
     }
 }
 
@@ -232,7 +242,7 @@ __global__ __launch_bounds__(kSearchThreads) void multinomial_search_kernel(
 // ---------------------------------------------------------------- launchers
 int launch_prefix(int kind, const float *lw, int32_t *anc, int32_t *off, int64_t P, uint64_t seed,
                   uint32_t instance, double *cumw, void *ws, int32_t *status,
-                  hipStream_t stream)
+                  hipStream_t stream, const Rows &rows)
 {
     const int64_t n = num_tiles(P);
     char *w = static_cast<char *>(ws);
@@ -240,10 +250,10 @@ int launch_prefix(int kind, const float *lw, int32_t *anc, int32_t *off, int64_t
     hipLaunchKernelGGL(tile_reduce_kernel, dim3((uint32_t)n), tb, 0, stream, lw, P, w);
     switch (kind) {
     case kStratified:
-        launch_fill<kStratified>(lw, anc, off, P, seed, instance, cumw, w, status, stream);
+        launch_fill<kStratified>(lw, anc, off, P, seed, instance, cumw, w, status, stream, rows);
         break;
     case kSystematic:
-        launch_fill<kSystematic>(lw, anc, off, P, seed, instance, cumw, w, status, stream);
+        launch_fill<kSystematic>(lw, anc, off, P, seed, instance, cumw, w, status, stream, rows);
         break;
     case kMultinomial: {
         double *C = cumw ? cumw : reinterpret_cast<double *>(w + ws_layout(P, true).cumw);
@@ -262,7 +272,7 @@ int launch_prefix(int kind, const float *lw, int32_t *anc, int32_t *off, int64_t
         const int64_t need = (P + per_block - 1) / per_block;
         const int64_t grid = need < 1 ? 1 : (need > 2048 ? 2048 : need);
         hipLaunchKernelGGL(multinomial_search_kernel, dim3((uint32_t)grid), dim3(kSearchThreads),
-                           smem, stream, C, anc, P, seed, instance, w);
+                           smem, stream, C, anc, P, seed, instance, w, rows);
         break;
     }
     default:

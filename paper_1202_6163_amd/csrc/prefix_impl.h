@@ -168,6 +168,20 @@ __device__ __forceinline__ double systematic_offset(uint64_t seed, uint32_t inst
     return unit32(philox(seed, 0u, instance, 0u, kTagSystematic).r0);
 }
 
+// N(c) for c < W by bisection over the draw indices [lo, hi) (N(c) is known
+// to lie there): one draw point per step, few registers.
+template <int KIND>
+__device__ int64_t count_below_bisect(double c, int64_t lo, int64_t hi, double delta,
+                                      uint64_t seed, uint32_t instance, double u_sys)
+{
+    while (lo < hi) {
+        const int64_t mid = lo + ((hi - lo) >> 1);
+        if (draw_point<KIND>(mid, delta, seed, instance, u_sys) < c) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
 // N(c) = #{i : x_i < c} for the non-decreasing stratified/systematic draw
 // points, or P when c >= W (draws at or past W belong to the last positive
 // tile). With e = floor(c / (W/P)), x_{e-2} < c <= x_{e+2} up to rounding, so
@@ -202,13 +216,7 @@ __device__ int64_t count_below(double c, int64_t P, double W, double delta, uint
             if (x[k] >= c) return s + k;
         }
     }
-    int64_t lo = 0, hi = P;  // fallback (not expected): bisection
-    while (lo < hi) {
-        const int64_t mid = lo + ((hi - lo) >> 1);
-        if (draw_point<KIND>(mid, delta, seed, instance, u_sys) < c) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
+    return count_below_bisect<KIND>(c, 0, P, delta, seed, instance, u_sys);  // not expected
 }
 
 // ------------------------------------------------------ phase 1: tile
@@ -598,15 +606,19 @@ __device__ void tile_offspring(int32_t *off, int64_t P, int64_t t, int64_t lo, i
             o[k] = (int32_t)sh_stop[4 * threadIdx.x + k] - (int32_t)sh_start[4 * threadIdx.x + k];
     } else {
         if (j0 >= P) return;
-        int64_t prev = threadIdx.x == 0
-                           ? lo
-                           : count_below<KIND>(Cs[4 * threadIdx.x - 1], P, W, delta, seed, instance,
-                                               u_sys);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int64_t c =
-                count_below<KIND>(Cs[4 * threadIdx.x + k], P, W, delta, seed, instance, u_sys);
-            o[k] = (int32_t)(c - prev);
+        // rare (heavy tiles only): bisection over the tile's draws [lo, hi), one
+        // count at a time, which keeps the kernel's registers low; C'_j = B_t
+        // (the tile's end) counts hi, also when hi = P takes draws at or past W
+        int64_t prev = lo;
+#pragma unroll 1
+        for (int k = -1; k < 4; ++k) {
+            const int e = 4 * (int)threadIdx.x + k;
+            int64_t c = lo;
+            if (e >= 0)
+                c = Cs[e] >= Cs[kTile - 1] ? hi
+                                           : count_below_bisect<KIND>(Cs[e], lo, hi, delta, seed,
+                                                                      instance, u_sys);
+            if (k >= 0) o[k] = (int32_t)(c - prev);
             prev = c;
         }
     }

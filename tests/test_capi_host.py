@@ -223,3 +223,27 @@ def test_sorted_variant_arguments(L):
                                    None) == L.RS_EWORKSPACE
     assert lib.resample_sorted(9, f(0x1000), f(0x2000), 10, 1, 0, f(0x90000), 1 << 30, None,
                                None) == L.RS_EINVAL
+
+
+def test_resample_and_copy_arguments(L):
+    lib = L.lib
+    f = ctypes.c_void_p
+    lw, anc, off, xi, xo, ws = (f(0x100000), f(0x200000), f(0x300000), f(0x400000), f(0x800000),
+                                f(0xC00000))
+    ok = dict(kind=L.METROPOLIS)
+
+    def call(kind=3, lw=lw, anc=anc, off=None, P=10, xi=xi, xo=xo, D=4, ws=ws, wsb=1 << 20):
+        return lib.resample_and_copy(kind, lw, anc, off, P, 8, 1, 0, xi, xo, D, ws, wsb, None,
+                                     None)
+    assert ok and call(P=0, lw=None, anc=None, xi=None, xo=None) == L.RS_OK
+    assert call(kind=9) == L.RS_EINVAL
+    assert call(anc=None) == L.RS_EINVAL
+    assert call(xi=None) == L.RS_EINVAL
+    assert call(D=0) == L.RS_EINVAL
+    assert call(off=off) == L.RS_EINVAL                      # Metropolis has no offspring
+    assert call(kind=L.MULTINOMIAL, off=off) == L.RS_EINVAL  # nor multinomial
+    assert call(xo=f(0x400010)) == L.RS_EINVAL               # x_out overlaps x_in
+    assert call(xo=f(0x200004)) == L.RS_EINVAL               # x_out overlaps anc
+    assert call(kind=L.STRATIFIED, ws=None) == L.RS_EINVAL
+    assert call(kind=L.STRATIFIED, wsb=8) == L.RS_EWORKSPACE
+    assert call(kind=L.SYSTEMATIC, off=f(0x200008)) == L.RS_EINVAL  # off overlaps anc

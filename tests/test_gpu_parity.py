@@ -460,3 +460,47 @@ def test_sorted_variant_ties_and_flags(rs, kind):
     st = torch.zeros(1, dtype=torch.int32, device="cuda")
     anc = host(rs.resample_sorted(kind, dev(bad), 1, 0, status=st))
     assert int(host(st)[0]) == rs.FLAG_NAN and np.array_equal(anc, np.arange(2000))
+
+
+# ----------------------------------------------------------------- fused resample + copy
+@pytest.mark.parametrize("kind", ["metropolis"] + PREFIX)
+@pytest.mark.parametrize("P,D", [(1, 4), (777, 3), (5000, 4), (100003, 8), (1 << 18, 4)])
+def test_resample_and_copy_equals_separate_calls(rs, kind, P, D):
+    seed, inst = 11, 4
+    lw = dev(workloads.normal_logweights(P, 1.0, seed))
+    x = dev(workloads.state_rows_exact(P, D))
+    off = (torch.full((P,), -1, dtype=torch.int32, device="cuda")
+           if kind in SORTED else None)
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    anc, xo = rs.resample_and_copy(kind, lw, x, seed, inst, B=24, off=off, status=st)
+    if kind == "metropolis":
+        ref = rs.resample_metropolis(lw, 24, seed, inst)
+    elif kind == "multinomial":
+        ref = rs.resample_multinomial(lw, seed, inst)
+    else:
+        ref_off = torch.empty_like(off)
+        ref = getattr(rs, f"resample_{kind}")(lw, seed, inst, off=ref_off)
+        assert torch.equal(off, ref_off)
+    assert int(host(st)[0]) == 0
+    assert torch.equal(anc, ref)
+    want, rc = oracle.permute_copy(host(anc), host(x))
+    assert rc == 0
+    assert np.array_equal(host(xo).view(np.int32), want.view(np.int32))
+
+
+@pytest.mark.parametrize("kind", ["metropolis"] + PREFIX)
+def test_resample_and_copy_small_groups_and_flags(rs, kind):
+    # few particles: several lanes share a Metropolis chain and split the row
+    lw = dev(workloads.normal_logweights(300, 2.0, 3))
+    x = dev(workloads.state_rows_exact(300, 16))
+    anc, xo = rs.resample_and_copy(kind, lw, x, 5, 0, B=200)
+    want, _ = oracle.permute_copy(host(anc), host(x))
+    assert np.array_equal(host(xo).view(np.int32), want.view(np.int32))
+    if kind != "metropolis":
+        bad = np.zeros(2000, dtype=np.float32)
+        bad[3] = np.nan
+        xb = dev(workloads.state_rows_exact(2000, 4))
+        st = torch.zeros(1, dtype=torch.int32, device="cuda")
+        anc, xo = rs.resample_and_copy(kind, dev(bad), xb, 1, 0, status=st)
+        assert int(host(st)[0]) == rs.FLAG_NAN
+        assert np.array_equal(host(anc), np.arange(2000)) and torch.equal(xo, xb)
