@@ -51,21 +51,27 @@ __host__ __device__ inline int64_t num_tiles(int64_t P) { return (P + kTile - 1)
 // kWindow-wide windows of draw indices (the unit of the fill's overflow blocks).
 __host__ __device__ inline int64_t num_windows(int64_t P) { return (P + kWindow - 1) / kWindow; }
 
-// Multinomial search: every kSubStride-th cumulative weight (the last of each
-// group of kSubStride) is kept in a compact array small enough to stage in
-// LDS (at most kSubMax doubles); the stride doubles beyond 2^20 particles.
-constexpr int64_t kSubMax = 16384;
+// Multinomial search: the particles are cut into kParts contiguous parts
+// (one per XCD of the MI355X: each part's cumulative weights stay in that
+// XCD's L2). Within part x the last C' of every group of sub_stride(P)
+// particles goes to a compact array, at most kSubMax doubles per part (staged
+// in LDS by the search); the groups are 16 particles (one 128-byte line) up to
+// 2^20 particles and double beyond.
+constexpr int kParts = 8;
+constexpr int64_t kSubMax = 8192;
+__host__ __device__ inline int64_t part_size(int64_t P) { return (P + kParts - 1) / kParts; }
 __host__ __device__ inline int64_t sub_stride(int64_t P)
 {
-    int64_t s = 64;
-    while ((P + s - 1) / s > kSubMax) s <<= 1;
+    int64_t s = 16;
+    while ((part_size(P) + s - 1) / s > kSubMax) s <<= 1;
     return s;
 }
-__host__ __device__ inline int64_t num_sub(int64_t P)
+__host__ __device__ inline int64_t sub_per_part(int64_t P)
 {
     const int64_t s = sub_stride(P);
-    return (P + s - 1) / s;
+    return (part_size(P) + s - 1) / s;
 }
+__host__ __device__ inline int64_t num_sub(int64_t P) { return kParts * sub_per_part(P); }
 
 __host__ __device__ inline WsLayout ws_layout(int64_t P, bool with_cumw)
 {

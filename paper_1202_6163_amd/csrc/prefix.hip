@@ -27,8 +27,9 @@
 // HBM traffic is two reads of lw and one write of anc (and/or off); the
 // cumulative weights are stored only on request. The multinomial draws are
 // unsorted, so that resampler stores C (launch 3m) and searches it per draw
-// (launch 4m): every 64th C' staged in LDS, then the 64 C' of the draw's
-// group in HBM.
+// (launch 4m): the particles are split in eight parts, one per XCD, each
+// searched by the blocks that XCD runs (every 16th C' of the part staged in
+// LDS, then one 128-byte line of C).
 //
 // Rounding: inside a tile C'_j = min(B_{t-1} + L_j, B_t), where L_j is a
 // zero-weight-aware running maximum of the tile's scan, and C'_j = B_t from
@@ -125,9 +126,9 @@ void launch_fill(const float *lw, int32_t *anc, int32_t *off, int64_t P, uint64_
 }
 
 // ------------------------------------------------------ multinomial
-// Launch 3m: one block per tile writes C' for the tile, and the last C' of
-// every kSubStride-wide group into the compact array ws.sub (the group that
-// holds P - 1 takes the C' at its padded end, which equals W like C'_{P-1}).
+// Launch 3m: one block per tile writes C' for the tile, and into ws.sub the
+// last C' of every sub_stride(P)-particle group of each part (the last group
+// of a part ends at the part's end).
 __global__ __launch_bounds__(kTileThreads) void cumulative_kernel(const float *__restrict__ lw,
                                                                   int64_t P, double *C,
                                                                   char *ws_raw)
@@ -147,12 +148,14 @@ __global__ __launch_bounds__(kTileThreads) void cumulative_kernel(const float *_
     double Cv[4];
     tile_cumulative(v, ws.h->m, Blo, ws.bound[t], Cs, Cv);
     store_cumw(C, P, t, Cv);
-    const int64_t S = sub_stride(P), ns = num_sub(P);
-    const int64_t e = t * kTile + 4 * (int64_t)threadIdx.x + 3;  // this thread's last element
-    if ((e + 1) % S == 0 && e / S < ns)
-        ws.sub[e / S] = Cv[3];
-    else if (S > kTile && t == num_tiles(P) - 1 && threadIdx.x == kTileThreads - 1)
-        ws.sub[ns - 1] = Cv[3];  // last group ends past the last tile
+    const int64_t Pp = part_size(P), S = sub_stride(P), ns = sub_per_part(P);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const int64_t e = t * kTile + 4 * (int64_t)threadIdx.x + m;
+        if (e >= P) break;
+        const int64_t x = e / Pp, local = e - x * Pp, end = min((x + 1) * Pp, P);
+        if ((local + 1) % S == 0 || e == end - 1) ws.sub[x * ns + local / S] = Cv[m];
+    }
 }
 
 // First index in [0, len) with a[i] > x, given a[len - 1] > x: branchless
@@ -168,72 +171,132 @@ __device__ __forceinline__ int64_t first_above(const double *a, int64_t len, dou
     return base;
 }
 
-// Launch 4m: a persistent grid of 1024-thread blocks. Each block stages
-// ws.sub (the last C' of every group of S = sub_stride(P) particles; at most
-// 128 KB) in LDS; each thread draws kDraws points (two per Philox block) and
-// locates them side by side (their memory round trips overlap): bisection
-// over the staged group ends, then over the group's S cumulative weights in
-// global memory (S = 64 up to 2^20 particles: six dependent reads within four
-// cache lines).
-constexpr int kDraws = 4;
+// Launch 4m: kParts x K blocks of 1024 threads; blocks b = x, x + kParts, ...
+// serve part x (the draws whose ancestor lies in it), so with the round-robin
+// placement of blocks on the XCDs one XCD searches one part and its slice of
+// C stays in that XCD's L2. A block walks its share of all draw pairs in
+// chunks: each thread draws kPairsPerThread pairs (one Philox block each) and
+// keeps those with C'[start - 1] <= x < C'[end - 1]; the kept draw indices go
+// to an LDS queue (wave-aggregated slots); then every thread takes queued
+// draws, redraws x, bisects the part's group ends staged in LDS and the
+// group's C' in HBM (16 values, one 128-byte line, up to 2^20 particles).
 constexpr int kSearchThreads = 1024;
+constexpr int kPairsPerThread = 8;
+constexpr int kChunkPairs = kSearchThreads * kPairsPerThread;
+
+__device__ __forceinline__ double multinomial_draw(uint64_t seed, uint32_t instance, int64_t i,
+                                                   double W, double capW)
+{
+    const Block4 b = philox(seed, (uint32_t)(i >> 1), instance, 0u, kTagMultinomial);
+    const double u = (i & 1) ? unit53(b.r2, b.r3) : unit53(b.r0, b.r1);
+    return fmin(u * W, capW);
+}
 
 __global__ __launch_bounds__(kSearchThreads) void multinomial_search_kernel(
     const double *__restrict__ C, int32_t *__restrict__ anc, int64_t P, uint64_t seed,
     uint32_t instance, char *ws_raw, Rows rows)
 {
     extern __shared__ double sh_sub[];
+    __shared__ int32_t sh_queue[2 * kChunkPairs];
+    __shared__ int32_t sh_count[2];
     const WsView ws = ws_view(ws_raw, P);
-    const int64_t S = sub_stride(P), ns = num_sub(P);
+    const int part = (int)(blockIdx.x % kParts);
+    const int64_t rank = blockIdx.x / kParts, per_part = gridDim.x / kParts;
+    const int64_t Pp = part_size(P), S = sub_stride(P), ns = sub_per_part(P);
+    const int64_t start = part * Pp, end = min(start + Pp, P);
+    const int64_t pairs = (P + 1) / 2;
     const int flags = ws.h->flags;
-    const double W = ws.h->W;
-    if (!flags) {
-        for (int64_t k = threadIdx.x; k < ns; k += kSearchThreads) sh_sub[k] = ws.sub[k];
-        __syncthreads();
-    }
-    const double capW = below(W);
-    const int64_t groups = (P + kDraws - 1) / kDraws;
-    for (int64_t q = blockIdx.x * (int64_t)kSearchThreads + threadIdx.x; q < groups;
-         q += (int64_t)gridDim.x * kSearchThreads) {
-        const int64_t i0 = q * kDraws;
-        if (flags) {
-            for (int k = 0; k < kDraws; ++k) {
-                if (i0 + k < P) {
-                    anc[i0 + k] = (int32_t)(i0 + k);
-                    if (rows.x_in) copy_row(rows, i0 + k, i0 + k, 0, 1);
+    if (flags) {  // identity, written by the blocks of part 0
+        if (part == 0) {
+            for (int64_t q = rank * kSearchThreads + threadIdx.x; q < pairs;
+                 q += per_part * kSearchThreads) {
+                for (int64_t i = 2 * q; i < min(2 * q + 2, P); ++i) {
+                    anc[i] = (int32_t)i;
+                    if (rows.x_in) copy_row(rows, i, i, 0, 1);
                 }
             }
-            continue;
         }
-        double x[kDraws];
+        return;
+    }
+    if (start >= P) return;  // fewer particles than parts
+    const int64_t groups = (end - start + S - 1) / S;
+    for (int64_t k = threadIdx.x; k < groups; k += kSearchThreads) sh_sub[k] = ws.sub[part * ns + k];
+    if (threadIdx.x == 0) {
+        sh_count[0] = 0;
+        sh_count[1] = 0;
+    }
+    const double W = ws.h->W, capW = below(W);
+    const double lo_bound = start > 0 ? C[start - 1] : -(double)INFINITY;
+    const double hi_bound = end < P ? C[end - 1] : (double)INFINITY;
+    __syncthreads();
+    const int lane = lane_id();
+    int parity = 0;
+    for (int64_t c0 = rank * kChunkPairs; c0 < pairs; c0 += per_part * kChunkPairs) {
+        // (1) draw the chunk's pairs; bit 2u + k of keep marks draw 2 q_u + k as ours
+        uint32_t keep = 0;
 #pragma unroll
-        for (int p = 0; p < kDraws / 2; ++p) {
-            const Block4 b = philox(seed, (uint32_t)(i0 / 2 + p), instance, 0u, kTagMultinomial);
-            x[2 * p] = fmin(unit53(b.r0, b.r1) * W, capW);
-            x[2 * p + 1] = fmin(unit53(b.r2, b.r3) * W, capW);
+        for (int u = 0; u < kPairsPerThread; ++u) {
+            const int64_t q = c0 + (int64_t)u * kSearchThreads + threadIdx.x;
+            if (q < pairs) {
+                const Block4 b = philox(seed, (uint32_t)q, instance, 0u, kTagMultinomial);
+                const double x0 = fmin(unit53(b.r0, b.r1) * W, capW);
+                const double x1 = fmin(unit53(b.r2, b.r3) * W, capW);
+                if (x0 >= lo_bound && x0 < hi_bound) keep |= 1u << (2 * u);
+                if (2 * q + 1 < P && x1 >= lo_bound && x1 < hi_bound) keep |= 2u << (2 * u);
+            }
         }
-        int64_t gk[kDraws];
+        // (2) queue slots: a wave-wide prefix of the counts, one LDS atomic per wave
+        const int cnt = __popc(keep);
+        int incl = cnt;
 #pragma unroll
-        for (int k = 0; k < kDraws; ++k) gk[k] = first_above(sh_sub, ns, x[k]);
-        int64_t j[kDraws];
-#pragma unroll
-        for (int k = 0; k < kDraws; ++k) {
-            const int64_t base = gk[k] * S;
-            j[k] = base + first_above(C + base, min(S, P - base), x[k]);
+        for (int off = 1; off < kWave; off <<= 1) {
+            const int y = __shfl_up(incl, off, kWave);
+            if (lane >= off) incl += y;
         }
-        if (i0 + kDraws <= P && (((uintptr_t)(anc + i0)) & 15) == 0) {
-            *reinterpret_cast<int4 *>(anc + i0) =
-                make_int4((int32_t)j[0], (int32_t)j[1], (int32_t)j[2], (int32_t)j[3]);
-        } else {
-#pragma unroll
-            for (int k = 0; k < kDraws; ++k)
-                if (i0 + k < P) anc[i0 + k] = (int32_t)j[k];
+        int base = 0;
+        if (lane == kWave - 1) base = atomicAdd(&sh_count[parity], incl);
+        base = __shfl(base, kWave - 1, kWave);
+        int pos = base + incl - cnt;
+        while (keep) {
+            const int bit = __ffs((int)keep) - 1;
+            keep &= keep - 1;
+            const int64_t q = c0 + (int64_t)(bit >> 1) * kSearchThreads + threadIdx.x;
+            sh_queue[pos++] = (int32_t)(2 * q + (bit & 1));
         }
-        if (rows.x_in) {
+        __syncthreads();
+        const int n = sh_count[parity];
+        if (threadIdx.x == 0) sh_count[parity ^ 1] = 0;  // the next chunk's counter
+        // (3) search the queued draws, two per thread at a time
+        for (int idx = threadIdx.x; idx < n; idx += 2 * kSearchThreads) {
+            int64_t i[2], j[2];
+            bool on[2];
 #pragma unroll
-            for (int k = 0; k < kDraws; ++k)
-                if (i0 + k < P) copy_row(rows, i0 + k, j[k], 0, 1);
+            for (int k = 0; k < 2; ++k) {
+                const int at = idx + k * kSearchThreads;
+                on[k] = at < n;
+                i[k] = on[k] ? sh_queue[at] : sh_queue[idx];
+            }
+            double x[2];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) x[k] = multinomial_draw(seed, instance, i[k], W, capW);
+            int64_t g[2];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) g[k] = first_above(sh_sub, groups, x[k]);
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int64_t gbase = start + g[k] * S;
+                j[k] = gbase + first_above(C + gbase, min(S, end - gbase), x[k]);
+            }
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                if (on[k]) {
+                    anc[i[k]] = (int32_t)j[k];
+                    if (rows.x_in) copy_row(rows, i[k], j[k], 0, 1);
+                }
+            }
         }
+        __syncthreads();  // the queue is free again
+        parity ^= 1;
     }
 }
 
@@ -259,7 +322,7 @@ int launch_prefix(int kind, const float *lw, int32_t *anc, int32_t *off, int64_t
         double *C = cumw ? cumw : reinterpret_cast<double *>(w + ws_layout(P, true).cumw);
         launch_table<kMultinomial>(P, seed, instance, w, status, nullptr, stream);
         hipLaunchKernelGGL(cumulative_kernel, dim3((uint32_t)n), tb, 0, stream, lw, P, C, w);
-        const size_t smem = (size_t)num_sub(P) * sizeof(double);
+        const size_t smem = (size_t)sub_per_part(P) * sizeof(double);
         static size_t granted = 0;  // dynamic LDS above the default needs the attribute
         if (smem > granted) {
             if (hipFuncSetAttribute(reinterpret_cast<const void *>(&multinomial_search_kernel),
@@ -268,9 +331,11 @@ int launch_prefix(int kind, const float *lw, int32_t *anc, int32_t *off, int64_t
                 return launch_status();
             granted = smem;
         }
-        const int64_t per_block = (int64_t)kDraws * kSearchThreads;
-        const int64_t need = (P + per_block - 1) / per_block;
-        const int64_t grid = need < 1 ? 1 : (need > 2048 ? 2048 : need);
+        // K blocks per part: one per CU of an XCD at most, a chunk each at least
+        const int64_t pairs = (P + 1) / 2;
+        int64_t K = (pairs + kChunkPairs - 1) / kChunkPairs;
+        K = K < 1 ? 1 : (K > 32 ? 32 : K);
+        const int64_t grid = kParts * K;
         hipLaunchKernelGGL(multinomial_search_kernel, dim3((uint32_t)grid), dim3(kSearchThreads),
                            smem, stream, C, anc, P, seed, instance, w, rows);
         break;

@@ -173,7 +173,7 @@ def offspring_of(anc):
 def check_offspring(off_g, anc_g):
     """The resampler's own offspring counts are exactly the counts of its ancestors."""
     assert np.array_equal(np.asarray(off_g), offspring_of(anc_g))
-SIZES = [1, 2, 3, 1023, 1024, 1025, 4097, 100003, 1 << 16]
+SIZES = [1, 2, 3, 9, 1023, 1024, 1025, 4097, 100003, 1 << 16]
 
 
 @pytest.mark.parametrize("kind", PREFIX)
