@@ -41,7 +41,7 @@ struct alignas(64) WsHeader {
 };
 
 struct WsLayout {
-    size_t header, tile_max, tile_sum, tile_flags, bound, count, win, sub, cumw, total;
+    size_t header, tile_max, tile_sum, tile_flags, bound, count, win, sub, part, cumw, total;
 };
 
 __host__ __device__ inline size_t ws_align(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -59,7 +59,12 @@ __host__ __device__ inline int64_t num_windows(int64_t P) { return (P + kWindow 
 // 2^20 particles and double beyond.
 constexpr int kParts = 8;
 constexpr int64_t kSubMax = 8192;
-__host__ __device__ inline int64_t part_size(int64_t P) { return (P + kParts - 1) / kParts; }
+// Parts are whole tiles, so a part's lower bound in C' is a tile boundary.
+__host__ __device__ inline int64_t part_size(int64_t P)
+{
+    const int64_t p = (P + kParts - 1) / kParts;
+    return (p + kTile - 1) / kTile * kTile;
+}
 __host__ __device__ inline int64_t sub_stride(int64_t P)
 {
     int64_t s = 16;
@@ -84,9 +89,12 @@ __host__ __device__ inline WsLayout ws_layout(int64_t P, bool with_cumw)
     L.bound = L.tile_flags + ws_align(n * sizeof(int32_t));
     L.count = L.bound + ws_align(n * sizeof(double));
     L.win = L.count + ws_align(n * sizeof(int32_t));
+    // the multinomial sections (group ends, draw parts, C) sit past the shared
+    // ones at the same offsets whatever the kind; only the size differs
     L.sub = L.win + ws_align((size_t)num_windows(P) * sizeof(int32_t));
-    L.cumw = L.sub + (with_cumw ? ws_align((size_t)num_sub(P) * sizeof(double)) : 0);
-    L.total = L.cumw + (with_cumw ? ws_align((size_t)P * sizeof(double)) : 0);
+    L.part = L.sub + ws_align((size_t)num_sub(P) * sizeof(double));
+    L.cumw = L.part + ws_align((size_t)P + 16);
+    L.total = with_cumw ? L.cumw + ws_align((size_t)P * sizeof(double)) : L.sub;
     return L;
 }
 

@@ -131,7 +131,8 @@ void launch_fill(const float *lw, int32_t *anc, int32_t *off, int64_t P, uint64_
 // of a part ends at the part's end).
 __global__ __launch_bounds__(kTileThreads) void cumulative_kernel(const float *__restrict__ lw,
                                                                   int64_t P, double *C,
-                                                                  char *ws_raw)
+                                                                  char *ws_raw, uint64_t seed,
+                                                                  uint32_t instance)
 {
     __shared__ double Cs[kTile];
     const WsView ws = ws_view(ws_raw, P);
@@ -156,6 +157,31 @@ __global__ __launch_bounds__(kTileThreads) void cumulative_kernel(const float *_
         const int64_t x = e / Pp, local = e - x * Pp, end = min((x + 1) * Pp, P);
         if ((local + 1) % S == 0 || e == end - 1) ws.sub[x * ns + local / S] = Cv[m];
     }
+    // The part of each of the tile's draws [t kTile, (t+1) kTile) (two Philox
+    // blocks per thread): part y holds C' in [B_{y Pp / kTile - 1}, the next
+    // part's bound), so the search reads one byte per draw instead of redrawing.
+    const double W = ws.h->W, capW = below(W);
+    const int parts = (int)((P + Pp - 1) / Pp);
+    double lo[kParts];
+#pragma unroll
+    for (int y = 1; y < kParts; ++y)
+        lo[y] = y < parts ? ws.bound[y * Pp / kTile - 1] : (double)INFINITY;
+    uint32_t ids = 0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int64_t q = t * (kTile / 2) + 2 * (int64_t)threadIdx.x + h;  // draws 2q, 2q+1
+        const Block4 b = philox(seed, (uint32_t)q, instance, 0u, kTagMultinomial);
+        const double x[2] = {fmin(unit53(b.r0, b.r1) * W, capW), fmin(unit53(b.r2, b.r3) * W, capW)};
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            uint32_t y = 0;
+#pragma unroll
+            for (int z = 1; z < kParts; ++z) y += lo[z] <= x[k] ? 1u : 0u;
+            ids |= y << (8 * (2 * h + k));
+        }
+    }
+    if (t * kTile + 4 * (int64_t)threadIdx.x < P)  // the array has 16 bytes of slack past P
+        reinterpret_cast<uint32_t *>(ws.part + t * kTile)[threadIdx.x] = ids;
 }
 
 // First index in [0, len) with a[i] > x, given a[len - 1] > x: branchless
@@ -174,15 +200,14 @@ __device__ __forceinline__ int64_t first_above(const double *a, int64_t len, dou
 // Launch 4m: kParts x K blocks of 1024 threads; blocks b = x, x + kParts, ...
 // serve part x (the draws whose ancestor lies in it), so with the round-robin
 // placement of blocks on the XCDs one XCD searches one part and its slice of
-// C stays in that XCD's L2. A block walks its share of all draw pairs in
-// chunks: each thread draws kPairsPerThread pairs (one Philox block each) and
-// keeps those with C'[start - 1] <= x < C'[end - 1]; the kept draw indices go
-// to an LDS queue (wave-aggregated slots); then every thread takes queued
-// draws, redraws x, bisects the part's group ends staged in LDS and the
-// group's C' in HBM (16 values, one 128-byte line, up to 2^20 particles).
+// C stays in that XCD's L2. A block scans the part bytes of its share of the
+// draws in chunks (16 per thread), queues the draws of its part in LDS
+// (wave-aggregated slots), then every thread takes queued draws, redraws x,
+// bisects the part's group ends staged in LDS and reads the group's 16 C'
+// (one 128-byte line, up to 2^20 particles) with eight 16-byte loads.
 constexpr int kSearchThreads = 1024;
-constexpr int kPairsPerThread = 8;
-constexpr int kChunkPairs = kSearchThreads * kPairsPerThread;
+constexpr int kIdsPerThread = 16;
+constexpr int kQueue = kSearchThreads * kIdsPerThread;
 
 __device__ __forceinline__ double multinomial_draw(uint64_t seed, uint32_t instance, int64_t i,
                                                    double W, double capW)
@@ -192,58 +217,66 @@ __device__ __forceinline__ double multinomial_draw(uint64_t seed, uint32_t insta
     return fmin(u * W, capW);
 }
 
+// First k in [0, n) with a[k] > x, given a[n - 1] > x (LDS, n < 2^31).
+__device__ __forceinline__ int first_above_lds(const double *a, int n, double x)
+{
+    int base = 0;
+    while (n > 1) {
+        const int half = n >> 1;
+        base = a[base + half - 1] <= x ? base + half : base;
+        n -= half;
+    }
+    return base;
+}
+
 __global__ __launch_bounds__(kSearchThreads) void multinomial_search_kernel(
     const double *__restrict__ C, int32_t *__restrict__ anc, int64_t P, uint64_t seed,
     uint32_t instance, char *ws_raw, Rows rows)
 {
     extern __shared__ double sh_sub[];
-    __shared__ int32_t sh_queue[2 * kChunkPairs];
+    __shared__ int32_t sh_queue[kQueue];
     __shared__ int32_t sh_count[2];
     const WsView ws = ws_view(ws_raw, P);
     const int part = (int)(blockIdx.x % kParts);
-    const int64_t rank = blockIdx.x / kParts, per_part = gridDim.x / kParts;
+    const int64_t rank = blockIdx.x / kParts, K = gridDim.x / kParts;
     const int64_t Pp = part_size(P), S = sub_stride(P), ns = sub_per_part(P);
     const int64_t start = part * Pp, end = min(start + Pp, P);
-    const int64_t pairs = (P + 1) / 2;
+    // this block's draws [d0, d1), a multiple of 16 wide
+    const int64_t span = ((P + K - 1) / K + kIdsPerThread - 1) / kIdsPerThread * kIdsPerThread;
+    const int64_t d0 = min(P, rank * span), d1 = min(P, d0 + span);
     const int flags = ws.h->flags;
     if (flags) {  // identity, written by the blocks of part 0
         if (part == 0) {
-            for (int64_t q = rank * kSearchThreads + threadIdx.x; q < pairs;
-                 q += per_part * kSearchThreads) {
-                for (int64_t i = 2 * q; i < min(2 * q + 2, P); ++i) {
-                    anc[i] = (int32_t)i;
-                    if (rows.x_in) copy_row(rows, i, i, 0, 1);
-                }
+            for (int64_t i = d0 + threadIdx.x; i < d1; i += kSearchThreads) {
+                anc[i] = (int32_t)i;
+                if (rows.x_in) copy_row(rows, i, i, 0, 1);
             }
         }
         return;
     }
-    if (start >= P) return;  // fewer particles than parts
-    const int64_t groups = (end - start + S - 1) / S;
-    for (int64_t k = threadIdx.x; k < groups; k += kSearchThreads) sh_sub[k] = ws.sub[part * ns + k];
+    if (start >= P) return;  // fewer tiles than parts
+    const int groups = (int)((end - start + S - 1) / S);
+    for (int k = threadIdx.x; k < groups; k += kSearchThreads) sh_sub[k] = ws.sub[part * ns + k];
     if (threadIdx.x == 0) {
         sh_count[0] = 0;
         sh_count[1] = 0;
     }
     const double W = ws.h->W, capW = below(W);
-    const double lo_bound = start > 0 ? C[start - 1] : -(double)INFINITY;
-    const double hi_bound = end < P ? C[end - 1] : (double)INFINITY;
+    const bool vec = S == 16 && (((uintptr_t)C) & 15) == 0;
     __syncthreads();
     const int lane = lane_id();
     int parity = 0;
-    for (int64_t c0 = rank * kChunkPairs; c0 < pairs; c0 += per_part * kChunkPairs) {
-        // (1) draw the chunk's pairs; bit 2u + k of keep marks draw 2 q_u + k as ours
+    for (int64_t c0 = d0; c0 < d1; c0 += kQueue) {
+        // (1) this thread's 16 part bytes; bit b of keep marks draw i0 + b as ours
+        const int64_t i0 = c0 + (int64_t)kIdsPerThread * threadIdx.x;
         uint32_t keep = 0;
+        if (i0 < d1) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(ws.part + i0);
+            const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-        for (int u = 0; u < kPairsPerThread; ++u) {
-            const int64_t q = c0 + (int64_t)u * kSearchThreads + threadIdx.x;
-            if (q < pairs) {
-                const Block4 b = philox(seed, (uint32_t)q, instance, 0u, kTagMultinomial);
-                const double x0 = fmin(unit53(b.r0, b.r1) * W, capW);
-                const double x1 = fmin(unit53(b.r2, b.r3) * W, capW);
-                if (x0 >= lo_bound && x0 < hi_bound) keep |= 1u << (2 * u);
-                if (2 * q + 1 < P && x1 >= lo_bound && x1 < hi_bound) keep |= 2u << (2 * u);
-            }
+            for (int b = 0; b < kIdsPerThread; ++b)
+                if (i0 + b < d1 && ((w4[b >> 2] >> (8 * (b & 3))) & 0xffu) == (uint32_t)part)
+                    keep |= 1u << b;
         }
         // (2) queue slots: a wave-wide prefix of the counts, one LDS atomic per wave
         const int cnt = __popc(keep);
@@ -260,8 +293,7 @@ __global__ __launch_bounds__(kSearchThreads) void multinomial_search_kernel(
         while (keep) {
             const int bit = __ffs((int)keep) - 1;
             keep &= keep - 1;
-            const int64_t q = c0 + (int64_t)(bit >> 1) * kSearchThreads + threadIdx.x;
-            sh_queue[pos++] = (int32_t)(2 * q + (bit & 1));
+            sh_queue[pos++] = (int32_t)(i0 + bit);
         }
         __syncthreads();
         const int n = sh_count[parity];
@@ -279,13 +311,27 @@ __global__ __launch_bounds__(kSearchThreads) void multinomial_search_kernel(
             double x[2];
 #pragma unroll
             for (int k = 0; k < 2; ++k) x[k] = multinomial_draw(seed, instance, i[k], W, capW);
-            int64_t g[2];
-#pragma unroll
-            for (int k = 0; k < 2; ++k) g[k] = first_above(sh_sub, groups, x[k]);
+            int64_t gbase[2], len[2];
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
-                const int64_t gbase = start + g[k] * S;
-                j[k] = gbase + first_above(C + gbase, min(S, end - gbase), x[k]);
+                gbase[k] = start + (int64_t)first_above_lds(sh_sub, groups, x[k]) * S;
+                len[k] = min(S, end - gbase[k]);
+            }
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                if (vec && len[k] == 16) {  // the whole line: count the C' <= x
+                    const double2 *g2 = reinterpret_cast<const double2 *>(C + gbase[k]);
+                    double2 c[8];
+#pragma unroll
+                    for (int h = 0; h < 8; ++h) c[h] = g2[h];
+                    int below_x = 0;
+#pragma unroll
+                    for (int h = 0; h < 8; ++h)
+                        below_x += (c[h].x <= x[k] ? 1 : 0) + (c[h].y <= x[k] ? 1 : 0);
+                    j[k] = gbase[k] + below_x;
+                } else {
+                    j[k] = gbase[k] + first_above(C + gbase[k], len[k], x[k]);
+                }
             }
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
@@ -321,7 +367,8 @@ int launch_prefix(int kind, const float *lw, int32_t *anc, int32_t *off, int64_t
     case kMultinomial: {
         double *C = cumw ? cumw : reinterpret_cast<double *>(w + ws_layout(P, true).cumw);
         launch_table<kMultinomial>(P, seed, instance, w, status, nullptr, stream);
-        hipLaunchKernelGGL(cumulative_kernel, dim3((uint32_t)n), tb, 0, stream, lw, P, C, w);
+        hipLaunchKernelGGL(cumulative_kernel, dim3((uint32_t)n), tb, 0, stream, lw, P, C, w, seed,
+                           instance);
         const size_t smem = (size_t)sub_per_part(P) * sizeof(double);
         static size_t granted = 0;  // dynamic LDS above the default needs the attribute
         if (smem > granted) {
@@ -332,8 +379,7 @@ int launch_prefix(int kind, const float *lw, int32_t *anc, int32_t *off, int64_t
             granted = smem;
         }
         // K blocks per part: one per CU of an XCD at most, a chunk each at least
-        const int64_t pairs = (P + 1) / 2;
-        int64_t K = (pairs + kChunkPairs - 1) / kChunkPairs;
+        int64_t K = (P + kQueue - 1) / kQueue;
         K = K < 1 ? 1 : (K > 32 ? 32 : K);
         const int64_t grid = kParts * K;
         hipLaunchKernelGGL(multinomial_search_kernel, dim3((uint32_t)grid), dim3(kSearchThreads),
