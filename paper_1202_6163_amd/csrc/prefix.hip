@@ -70,8 +70,13 @@ __global__ __launch_bounds__(kTileThreads) void table_kernel(int64_t P, uint64_t
     const int64_t n = num_tiles(P);
     double *bound = LDS ? sh_tab : ws.bound;
     int32_t *count = LDS ? reinterpret_cast<int32_t *>(sh_tab + n) : ws.count;
-    table_body<KIND>(P, seed, instance, ws_raw, status, lse_out, bound, count, eps, B_max, B_used);
+    table_body<KIND>(P, seed, instance, ws_raw, status, lse_out, bound, count, eps, B_max, B_used,
+                     blockIdx.x, gridDim.x);
 }
+
+// Stratified/systematic tables with LDS scratch split the counts over up to
+// kTableParts blocks (one tile per thread); the rest run one block.
+constexpr int kTableParts = 8;
 
 template <int KIND>
 void launch_table(int64_t P, uint64_t seed, uint32_t instance, char *w, int32_t *status,
@@ -81,8 +86,14 @@ void launch_table(int64_t P, uint64_t seed, uint32_t instance, char *w, int32_t 
     const int64_t n = num_tiles(P);
     if (n <= kTableLdsTiles) {
         const size_t smem = (size_t)n * (sizeof(double) + sizeof(int32_t));
-        hipLaunchKernelGGL((table_kernel<KIND, true>), dim3(1), dim3(kTileThreads), smem, stream,
-                           P, seed, instance, w, status, lse_out, eps, B_max, B_used);
+        int64_t parts = 1;
+        if (KIND == kStratified || KIND == kSystematic) {
+            parts = (n + kTileThreads - 1) / kTileThreads;
+            parts = parts > kTableParts ? kTableParts : parts;
+        }
+        hipLaunchKernelGGL((table_kernel<KIND, true>), dim3((uint32_t)parts), dim3(kTileThreads),
+                           smem, stream, P, seed, instance, w, status, lse_out, eps, B_max,
+                           B_used);
     } else {
         hipLaunchKernelGGL((table_kernel<KIND, false>), dim3(1), dim3(kTileThreads), 0, stream, P,
                            seed, instance, w, status, lse_out, eps, B_max, B_used);

@@ -380,12 +380,24 @@ __device__ inline TableSums boundaries(const WsView &ws, int64_t P, double *boun
 }
 
 // The table launch: boundaries, and for stratified/systematic the draw
-// counts below every boundary, into the workspace. `bound` and `count` are
-// scratch for n tiles (LDS when they fit, else the workspace arrays).
+// counts below every boundary and the owners of the overflow windows, into
+// the workspace. `bound` and `count` are scratch for n tiles (LDS when they
+// fit, else the workspace arrays). With parts > 1 (LDS scratch only) the
+// launch has that many blocks: each rebuilds all boundaries (the same bits)
+// and counts and publishes its own share of the tiles; block 0 writes the
+// header.
+//
+// Overflow windows: the draws of tile t beyond its fill block's slots,
+// [M_t, hi_t) with M_t = (lo_t & ~3) + kChunk, go to the kWindow-wide windows
+// they meet. Only the tile holding a window's first draw can reach into it
+// (a later tile's remainder starts more than kWindow past its own first
+// draw), so that tile writes the window's entry: itself or -1. Every entry
+// is written exactly once.
 template <int KIND>
 __device__ void table_body(int64_t P, uint64_t seed, uint32_t instance, char *ws_raw,
                            int32_t *status, double *lse_out, double *bound, int32_t *count,
-                           double eps = 0.0, uint32_t B_max = 0, uint32_t *B_used = nullptr)
+                           double eps = 0.0, uint32_t B_max = 0, uint32_t *B_used = nullptr,
+                           int part = 0, int parts = 1)
 {
     const WsView ws = ws_view(ws_raw, P);
     WsHeader *h = ws.h;
@@ -394,7 +406,7 @@ __device__ void table_body(int64_t P, uint64_t seed, uint32_t instance, char *ws
     const bool staged = bound != ws.bound;
     const TableSums sums = boundaries(ws, P, bound);
     if (sums.flags) {
-        if (tid == 0) {
+        if (tid == 0 && part == 0) {
             h->flags = sums.flags;
             h->B = 0;
             if (B_used) *B_used = 0;
@@ -405,49 +417,27 @@ __device__ void table_body(int64_t P, uint64_t seed, uint32_t instance, char *ws
         }
         return;
     }
-    const int64_t per = (n + kTileThreads - 1) / kTileThreads;
-    const int64_t t0 = min(n, (int64_t)tid * per), t1 = min(n, t0 + per);
+    const int64_t u0 = n * part / parts, u1 = n * (part + 1) / parts;  // this block's tiles
     const double W = sums.W, delta = W / (double)P;
     if (staged)
-        for (int64_t t = t0; t < t1; ++t) ws.bound[t] = bound[t];
+        for (int64_t t = u0 + tid; t < u1; t += kTileThreads) ws.bound[t] = bound[t];
     if (KIND == kStratified || KIND == kSystematic) {
         const double u_sys = KIND == kSystematic ? systematic_offset(seed, instance) : 0.0;
-        if (per <= kRegTiles) {
-            int32_t c[kRegTiles];
-#pragma unroll
-            for (int k = 0; k < kRegTiles; ++k)
-                c[k] = t0 + k < t1 ? (int32_t)count_below<KIND>(bound[t0 + k], P, W, delta, seed,
-                                                                 instance, u_sys)
-                                   : 0;
-#pragma unroll
-            for (int k = 0; k < kRegTiles; ++k) {
-                if (t0 + k < t1) {
-                    count[t0 + k] = c[k];
-                    if (staged) ws.count[t0 + k] = c[k];
-                }
-            }
-        } else {
-            for (int64_t t = t0; t < t1; ++t) {
-                const int32_t cnt =
-                    (int32_t)count_below<KIND>(bound[t], P, W, delta, seed, instance, u_sys);
-                count[t] = cnt;
-                if (staged) ws.count[t] = cnt;
-            }
+        // counts of tiles [u0 - 1, u1): the one before gives the first tile's lo
+        for (int64_t t = (u0 > 0 ? u0 - 1 : 0) + tid; t < u1; t += kTileThreads) {
+            const int32_t c = (int32_t)count_below<KIND>(bound[t], P, W, delta, seed, instance, u_sys);
+            count[t] = c;
+            if (staged && t >= u0) ws.count[t] = c;
         }
-        // overflow windows: a tile's draws beyond its block's slots, [M_t, hi_t) with
-        // M_t = (lo_t & ~3) + kChunk, go to the kWindow-wide windows they meet; the
-        // overflow parts of two tiles lie more than kWindow apart, so a window has
-        // at most one owner. Unowned windows hold -1.
-        const int64_t nw = num_windows(P);
-        for (int64_t q = tid; q < nw; q += kTileThreads) ws.win[q] = -1;
-        __syncthreads();  // also: count[t0 - 1] belongs to the previous thread
-        for (int64_t t = t0; t < t1; ++t) {
+        __syncthreads();
+        for (int64_t t = u0 + tid; t < u1; t += kTileThreads) {
             const int64_t lo = t > 0 ? count[t - 1] : 0, hi = count[t];
             const int64_t M = (lo & ~(int64_t)3) + kChunk;
-            for (int64_t q = M / kWindow; M < hi && q * kWindow < hi; ++q) ws.win[q] = (int32_t)t;
+            for (int64_t q = (lo + kWindow - 1) / kWindow; q * kWindow < hi; ++q)
+                ws.win[q] = (M < hi && M < (q + 1) * kWindow) ? (int32_t)t : -1;
         }
     }
-    if (tid == 0) {
+    if (tid == 0 && part == 0) {
         h->m = sums.m;
         h->W = W;
         h->delta = delta;
