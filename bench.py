@@ -278,22 +278,31 @@ def ceilings(torch, rs, G, lw, metro_iter_per_s):
 
 def load_traffic(kernel):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources (null otherwise)."""
+    was taken on the current sources of that kernel family (null otherwise)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         rec = json.load(open(path))
     except (OSError, ValueError):
         return None
     entry = rec.get(kernel)
-    if not entry or entry.get("source_sha256") != source_hash():
+    if not entry or entry.get("source_sha256") != source_hash(kernel):
         return None
     return entry.get("bytes_per_launch")
 
 
-def source_hash():
+# The sources each kernel family is compiled from (what invalidates its counters).
+KERNEL_SOURCES = {
+    "metropolis": ["metropolis.hip", "metropolis_impl.h", "common.h", "launch.h"],
+    "permute_copy": ["misc.hip", "common.h", "launch.h"],
+    "stratified": ["prefix.hip", "prefix_impl.h", "prefix.h", "analysis.h", "common.h", "launch.h"],
+    "multinomial": ["prefix.hip", "prefix_impl.h", "prefix.h", "analysis.h", "common.h", "launch.h"],
+}
+
+
+def source_hash(kernel):
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1202_6163_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    for name in sorted(KERNEL_SOURCES[kernel]):
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode() + f.read())
     return h.hexdigest()

@@ -298,6 +298,20 @@ int rs_batch_plan_init(rs_batch_plan *plan, const rs_instance *descs, int32_t n,
                        size_t ws_bytes, void *host_staging, hipStream_t stream);
 /* Run a batch (asynchronous on `stream`; graph-capturable). */
 int resample_batch(const rs_batch_plan *plan, hipStream_t stream);
+/* As resample_batch with instance_add added to every instance's Philox
+ * instance word (the same plan serves every time step of a set of filters:
+ * instance = t gives each step fresh draws). resample_batch is
+ * resample_batch_at(plan, 0, stream). */
+int resample_batch_at(const rs_batch_plan *plan, uint32_t instance_add, hipStream_t stream);
+/*
+ * acc[k] += lse_k - log P_k for every instance k of the plan's last run: the
+ * log of its mean weight, the likelihood factor of Sec. 1's weighting step
+ * (lse_k = log sum_i exp(lw_i) from the instance's table). Stratified and
+ * systematic instances only; Metropolis and empty instances add NaN, and
+ * flagged weights NaN (NaN or +inf present) or -inf (all -inf).
+ *   acc [device] double[n_instances]. Graph-capturable.
+ */
+int rs_batch_log_mean_weight(const rs_batch_plan *plan, double *acc, hipStream_t stream);
 
 /*
  * Bootstrap particle filter around the resampler (Sec. 1: initialisation,
@@ -314,6 +328,18 @@ int resample_batch(const rs_batch_plan *plan, hipStream_t stream);
  *   q, r           noise variances (q >= 0, r > 0); t >= 1 for a step
  */
 int filter_init(float *x, int64_t P, int32_t D, uint64_t seed, hipStream_t stream);
+/*
+ * K filters at once (particle MCMC evaluates K parameter values per step):
+ * filter k holds rows [k P, (k+1) P) of x (and of lw), draws with Philox key
+ * seed + k and uses the noise variance q[k] (q: device double[K], each >= 0),
+ * so it computes exactly what filter_init / filter_propagate_weight compute
+ * for one filter with key seed + k and q = q[k]. A, y, r are shared.
+ */
+int filter_init_batch(float *x, int32_t K, int64_t P, int32_t D, uint64_t seed,
+                      hipStream_t stream);
+int filter_propagate_weight_batch(const float *x_in, float *x_out, float *lw, int32_t K, int64_t P,
+                                  int32_t D, const double *A, const float *y, const double *q,
+                                  double r, uint64_t seed, uint32_t t, hipStream_t stream);
 int filter_propagate_weight(const float *x_in, float *x_out, float *lw, int64_t P, int32_t D,
                             const double *A, const float *y, double q, double r, uint64_t seed,
                             uint32_t t, hipStream_t stream);

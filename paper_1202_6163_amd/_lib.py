@@ -89,6 +89,12 @@ def _load():
         "rs_probe_gather": (ctypes.c_int, [vp, i64, i64, i64, u32, vp, vp]),
         "rs_probe_philox": (ctypes.c_int, [u64, i64, i64, vp, vp]),
         "filter_init": (ctypes.c_int, [vp, i64, ctypes.c_int32, u64, vp]),
+        "filter_init_batch": (ctypes.c_int, [vp, ctypes.c_int32, i64, ctypes.c_int32, u64, vp]),
+        "filter_propagate_weight_batch": (ctypes.c_int, [vp, vp, vp, ctypes.c_int32, i64,
+                                                         ctypes.c_int32, vp, vp, vp,
+                                                         ctypes.c_double, u64, u32, vp]),
+        "resample_batch_at": (ctypes.c_int, [ctypes.POINTER(BatchPlan), u32, vp]),
+        "rs_batch_log_mean_weight": (ctypes.c_int, [ctypes.POINTER(BatchPlan), vp, vp]),
         "filter_propagate_weight": (ctypes.c_int, [vp, vp, vp, i64, ctypes.c_int32, vp, vp,
                                                    ctypes.c_double, ctypes.c_double, u64, u32,
                                                    vp]),

@@ -314,6 +314,36 @@ def filter_init(x, seed, stream=None):
     return x
 
 
+def filter_init_batch(x, K, seed, stream=None):
+    """x[K P, D] <- initial particles of K filters (filter k: key seed + k)."""
+    _need(x, torch.float32, "x")
+    KP, D = x.shape
+    if KP % K:
+        raise ValueError("x must hold K P rows")
+    check(lib.filter_init_batch(_ptr(x), int(K), KP // K, D, int(seed), _stream_handle(stream)),
+          "filter_init_batch")
+    return x
+
+
+def filter_propagate_weight_batch(x_in, A, y_t, q, r, seed, t, K, x_out, lw, stream=None):
+    """One step of K filters at time word t: rows of filter k use key seed + k
+    and variance q[k] (float64 device tensor of K)."""
+    _need(x_in, torch.float32, "x_in")
+    KP, D = x_in.shape
+    if KP % K:
+        raise ValueError("x_in must hold K P rows")
+    _need(x_out, torch.float32, "x_out", KP * D)
+    _need(lw, torch.float32, "lw", KP)
+    _need(A, torch.float64, "A", D * D)
+    _need(y_t, torch.float32, "y_t", D)
+    _need(q, torch.float64, "q", K)
+    check(lib.filter_propagate_weight_batch(_ptr(x_in), _ptr(x_out), _ptr(lw), int(K), KP // K, D,
+                                            _ptr(A), _ptr(y_t), _ptr(q), float(r), int(seed),
+                                            int(t), _stream_handle(stream)),
+          "filter_propagate_weight_batch")
+    return x_out, lw
+
+
 def filter_propagate_weight(x_in, A, y_t, q, r, seed, t, x_out=None, lw=None, stream=None):
     """One propagation + weighting step at time t >= 1; returns (x_out, lw)."""
     _need(x_in, torch.float32, "x_in")

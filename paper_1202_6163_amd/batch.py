@@ -83,9 +83,24 @@ class Batch:
                                      if self.staging is not None else None,
                                      _stream_handle(stream)), "rs_batch_plan_init")
 
-    def run(self, stream=None):
-        check(lib.resample_batch(ctypes.byref(self.plan), _stream_handle(stream)),
-              "resample_batch")
+    def run(self, stream=None, instance_add=0):
+        """Resample every instance; instance_add is added to each instance's
+        Philox instance word (e.g. the time step of a set of filters)."""
+        if instance_add:
+            check(lib.resample_batch_at(ctypes.byref(self.plan), int(instance_add),
+                                        _stream_handle(stream)), "resample_batch_at")
+        else:
+            check(lib.resample_batch(ctypes.byref(self.plan), _stream_handle(stream)),
+                  "resample_batch")
+
+    def add_log_mean_weight(self, acc, stream=None):
+        """acc[k] += log mean weight of instance k (stratified/systematic) from
+        the last run; acc: float64 device tensor of n instances."""
+        if acc.dtype != torch.float64 or acc.numel() != self.plan.n_instances or not acc.is_cuda:
+            raise ValueError("acc must be a float64 device tensor with one entry per instance")
+        check(lib.rs_batch_log_mean_weight(ctypes.byref(self.plan),
+                                           ctypes.c_void_p(acc.data_ptr()),
+                                           _stream_handle(stream)), "rs_batch_log_mean_weight")
 
     @property
     def particles(self):

@@ -46,7 +46,8 @@ __global__ __launch_bounds__(kThreads) void batch_tile_kernel(const BatchInstanc
 
 __global__ __launch_bounds__(kThreads) void batch_table_kernel(const BatchInstance *insts,
                                                                const int32_t *items,
-                                                               int32_t n_items, int use_lds)
+                                                               int32_t n_items, int use_lds,
+                                                               uint32_t instance_add)
 {
     extern __shared__ double sh_tab[];
     for (int32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
@@ -57,10 +58,11 @@ __global__ __launch_bounds__(kThreads) void batch_table_kernel(const BatchInstan
         const bool lds = use_lds != 0;  // LDS sized for the largest table of the batch
         double *bound = lds ? sh_tab : ws.bound;
         int32_t *count = lds ? reinterpret_cast<int32_t *>(sh_tab + n) : ws.count;
+        const uint32_t inst = I.instance + instance_add;
         if (I.kind == kStratified)
-            table_body<kStratified>(I.P, I.seed, I.instance, I.ws, I.status, nullptr, bound, count);
+            table_body<kStratified>(I.P, I.seed, inst, I.ws, I.status, nullptr, bound, count);
         else
-            table_body<kSystematic>(I.P, I.seed, I.instance, I.ws, I.status, nullptr, bound, count);
+            table_body<kSystematic>(I.P, I.seed, inst, I.ws, I.status, nullptr, bound, count);
     }
 }
 
@@ -68,8 +70,8 @@ __global__ __launch_bounds__(kThreads) void batch_table_kernel(const BatchInstan
 // copy of their rows. sh_anc holds the item's ancestors for the copy; w is
 // LDS-staged weights or the instance's lw.
 template <int UNROLL>
-__device__ void metropolis_item(const BatchInstance &I, int64_t first, int64_t count,
-                                float *staged, int32_t *sh_anc)
+__device__ void metropolis_item(const BatchInstance &I, uint32_t inst, int64_t first,
+                                int64_t count, float *staged, int32_t *sh_anc)
 {
     const uint32_t P = (uint32_t)I.P;
     const float *w = I.lw;
@@ -82,7 +84,7 @@ __device__ void metropolis_item(const BatchInstance &I, int64_t first, int64_t c
     for (int64_t r = threadIdx.x; r < count; r += kThreads) {
         const uint32_t i = (uint32_t)(first + r);
         fl |= mh::weight_flags(w[i]);
-        const int32_t a = (int32_t)mh::chain<UNROLL>(w, P, I.B, I.seed, I.instance, i);
+        const int32_t a = (int32_t)mh::chain<UNROLL>(w, P, I.B, I.seed, inst, i);
         I.anc[i] = a;
         if (I.x_in) sh_anc[r] = a;
     }
@@ -99,7 +101,8 @@ template <int UNROLL>
 __global__ __launch_bounds__(kThreads) void batch_main_kernel(const BatchInstance *insts,
                                                               const int2 *items, int32_t n_items,
                                                               int32_t chains_per_item,
-                                                              int64_t lds_max_p)
+                                                              int64_t lds_max_p,
+                                                              uint32_t instance_add)
 {
     extern __shared__ double sh_main[];  // [kChunk ints | union(kTile doubles, staged lw)]
     int32_t *sh_anc = reinterpret_cast<int32_t *>(sh_main);
@@ -109,16 +112,18 @@ __global__ __launch_bounds__(kThreads) void batch_main_kernel(const BatchInstanc
         __syncthreads();
         const int2 item = items[it];
         const BatchInstance &I = insts[item.x];
+        const uint32_t inst = I.instance + instance_add;
         if (I.kind == kMetropolisKind) {
             const int64_t first = (int64_t)item.y * chains_per_item;
             const int64_t count = min((int64_t)chains_per_item, I.P - first);
-            metropolis_item<UNROLL>(I, first, count, I.P <= lds_max_p ? staging : nullptr, sh_anc);
+            metropolis_item<UNROLL>(I, inst, first, count, I.P <= lds_max_p ? staging : nullptr,
+                                    sh_anc);
         } else if (I.kind == kStratified) {
-            fill_body<kStratified, false>(I.lw, I.anc, I.off, I.P, I.seed, I.instance, nullptr, I.ws,
+            fill_body<kStratified, false>(I.lw, I.anc, I.off, I.P, I.seed, inst, nullptr, I.ws,
                                           item.y, I.x_in, I.x_out, I.D, I.status, Cs, sh_anc,
                                           nullptr);
         } else {
-            fill_body<kSystematic, false>(I.lw, I.anc, I.off, I.P, I.seed, I.instance, nullptr, I.ws,
+            fill_body<kSystematic, false>(I.lw, I.anc, I.off, I.P, I.seed, inst, nullptr, I.ws,
                                           item.y, I.x_in, I.x_out, I.D, I.status, Cs, sh_anc,
                                           nullptr);
         }
@@ -126,6 +131,19 @@ __global__ __launch_bounds__(kThreads) void batch_main_kernel(const BatchInstanc
 }
 
 uint32_t grid_of(int32_t items, int32_t blocks) { return (uint32_t)max(1, min(items, blocks)); }
+
+// acc[k] += log of instance k's mean weight, lse_k - log P_k (the likelihood
+// factor of Sec. 1's weighting step), from the header its table left; NaN
+// for instances without a table (Metropolis, P = 0).
+__global__ __launch_bounds__(kThreads) void batch_log_mean_weight_kernel(const BatchInstance *insts,
+                                                                         int32_t n, double *acc)
+{
+    for (int32_t k = blockIdx.x * kThreads + threadIdx.x; k < n; k += gridDim.x * kThreads) {
+        const BatchInstance &I = insts[k];
+        const bool table = I.ws && I.P > 0 && I.kind != kMetropolisKind;
+        acc[k] += table ? ws_view(I.ws, I.P).h->lse - log((double)I.P) : (double)NAN;
+    }
+}
 
 }  // namespace
 
@@ -140,7 +158,7 @@ int launch_batch(const BatchLaunch &L, hipStream_t stream)
         const size_t smem = use_lds ? (size_t)n * (sizeof(double) + sizeof(int32_t)) : 0;
         hipLaunchKernelGGL(batch_table_kernel, dim3(grid_of(L.n_table_items, L.blocks)),
                            dim3(kThreads), smem, stream, L.insts, L.table_items, L.n_table_items,
-                           use_lds);
+                           use_lds, L.instance_add);
     }
     if (L.n_main_items > 0) {
         const size_t smem = L.smem_main;
@@ -156,7 +174,7 @@ int launch_batch(const BatchLaunch &L, hipStream_t stream)
             granted = smem;                                                                      \
         }                                                                                        \
         hipLaunchKernelGGL(batch_main_kernel<U>, grid, block, smem, stream, L.insts, L.main_items, \
-                           L.n_main_items, L.chains_per_item, L.lds_max_p);                      \
+                           L.n_main_items, L.chains_per_item, L.lds_max_p, L.instance_add);      \
         break;                                                                                   \
     }
         switch (L.unroll) {
@@ -169,6 +187,15 @@ int launch_batch(const BatchLaunch &L, hipStream_t stream)
         }
 #undef RS_BATCH_CASE
     }
+    return launch_status();
+}
+
+int launch_batch_log_mean_weight(const BatchInstance *insts, int32_t n, double *acc,
+                                 hipStream_t stream)
+{
+    const uint32_t grid = (uint32_t)max(1, min((n + kThreads - 1) / kThreads, 1024));
+    hipLaunchKernelGGL(batch_log_mean_weight_kernel, dim3(grid), dim3(kThreads), 0, stream, insts,
+                       n, acc);
     return launch_status();
 }
 

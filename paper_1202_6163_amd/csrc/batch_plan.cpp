@@ -224,6 +224,19 @@ int rs_batch_plan_init(rs_batch_plan *plan, const rs_instance *descs, int32_t n,
 
 int resample_batch(const rs_batch_plan *plan, hipStream_t stream)
 {
+    return resample_batch_at(plan, 0u, stream);
+}
+
+int rs_batch_log_mean_weight(const rs_batch_plan *plan, double *acc, hipStream_t stream)
+{
+    if (!plan || !plan->dev || plan->n_instances < 1 || !acc) return RS_EINVAL;
+    const rs::BatchInstance *insts = static_cast<const rs::BatchInstance *>(plan->dev);
+    const int rc = rs::launch_batch_log_mean_weight(insts, plan->n_instances, acc, stream);
+    return rc == 0 ? RS_OK : RS_EHIP;
+}
+
+int resample_batch_at(const rs_batch_plan *plan, uint32_t instance_add, hipStream_t stream)
+{
     if (!plan || !plan->dev || plan->n_instances < 1) return RS_EINVAL;
     const unsigned char *base = static_cast<const unsigned char *>(plan->dev);
     rs::BatchLaunch L;
@@ -240,6 +253,7 @@ int resample_batch(const rs_batch_plan *plan, hipStream_t stream)
     L.lds_max_p = plan->lds_max_p;
     L.max_table_tiles = plan->max_table_tiles;
     L.smem_main = (size_t)plan->smem_main;
+    L.instance_add = instance_add;
     const int rc = rs::launch_batch(L, stream);
     return rc == 0 ? RS_OK : (rc == -1 ? RS_EINVAL : RS_EHIP);
 }

@@ -287,7 +287,16 @@ int filter_init(float *x, int64_t P, int32_t D, uint64_t seed, hipStream_t strea
 {
     if (P == 0) return RS_OK;
     if (!x || P < 0 || P > kMaxP || D < 1 || D > 64) return RS_EINVAL;
-    return map_rc(rs::launch_filter_init(x, P, D, seed, stream));
+    return map_rc(rs::launch_filter_init(x, P, 1, D, seed, stream));
+}
+
+int filter_init_batch(float *x, int32_t K, int64_t P, int32_t D, uint64_t seed,
+                      hipStream_t stream)
+{
+    if (P == 0 || K == 0) return RS_OK;
+    if (!x || K < 0 || P < 0 || P > kMaxP || D < 1 || D > 64) return RS_EINVAL;
+    if ((int64_t)K * P > ((int64_t)1 << 40) / D) return RS_EINVAL;
+    return map_rc(rs::launch_filter_init(x, P, K, D, seed, stream));
 }
 
 int filter_propagate_weight(const float *x_in, float *x_out, float *lw, int64_t P, int32_t D,
@@ -302,7 +311,26 @@ int filter_propagate_weight(const float *x_in, float *x_out, float *lw, int64_t 
     if (overlaps(x_in, rows, x_out, rows) || overlaps(lw, 4 * (size_t)P, x_out, rows) ||
         overlaps(lw, 4 * (size_t)P, x_in, rows))
         return RS_EINVAL;
-    return map_rc(rs::launch_filter_step(x_in, x_out, lw, P, D, A, y, q, r, seed, t, stream));
+    return map_rc(
+        rs::launch_filter_step(x_in, x_out, lw, P, 1, D, A, y, q, nullptr, r, seed, t, stream));
+}
+
+int filter_propagate_weight_batch(const float *x_in, float *x_out, float *lw, int32_t K, int64_t P,
+                                  int32_t D, const double *A, const float *y, const double *q,
+                                  double r, uint64_t seed, uint32_t t, hipStream_t stream)
+{
+    if (P == 0 || K == 0) return RS_OK;
+    if (!x_in || !x_out || !lw || !A || !y || !q || K < 0 || P < 0 || P > kMaxP || D < 1 ||
+        D > 64)
+        return RS_EINVAL;
+    if ((int64_t)K * P > ((int64_t)1 << 40) / D) return RS_EINVAL;
+    if (!(r > 0.0)) return RS_EINVAL;
+    const size_t n = (size_t)K * (size_t)P, rows = n * (size_t)D * sizeof(float);
+    if (overlaps(x_in, rows, x_out, rows) || overlaps(lw, 4 * n, x_out, rows) ||
+        overlaps(lw, 4 * n, x_in, rows))
+        return RS_EINVAL;
+    return map_rc(
+        rs::launch_filter_step(x_in, x_out, lw, P, K, D, A, y, 0.0, q, r, seed, t, stream));
 }
 
 int rs_log_u_table(float *approx, float *exact, hipStream_t stream)

@@ -13,6 +13,11 @@
 // matrix-vector product and the weight accumulate in binary64 and round to
 // binary32 state once per component. Rows are read and written as 16-byte
 // vectors when D is a multiple of 4.
+//
+// Batches of K filters (particle MCMC evaluates many parameter values at
+// once): filter k owns rows [k P, (k+1) P), draws with Philox key seed + k and
+// may have its own noise variance q_k, so it computes exactly what a single
+// filter with key seed + k and variance q_k computes.
 #include <hip/hip_runtime.h>
 
 #include "common.h"
@@ -43,22 +48,23 @@ __device__ __forceinline__ void normals(uint64_t seed, uint32_t i, uint32_t t, i
 }
 
 __global__ __launch_bounds__(kFilterThreads) void filter_init_kernel(float *__restrict__ x,
-                                                                     int64_t P, int D,
+                                                                     int64_t P, int64_t K, int D,
                                                                      uint64_t seed)
 {
     double z[kMaxD];
-    for (int64_t i = blockIdx.x * (int64_t)kFilterThreads + threadIdx.x; i < P;
-         i += (int64_t)gridDim.x * kFilterThreads) {
-        normals(seed, (uint32_t)i, 0u, D, z);
-        for (int d = 0; d < D; ++d) x[i * D + d] = (float)z[d];
+    for (int64_t g = blockIdx.x * (int64_t)kFilterThreads + threadIdx.x; g < K * P;
+         g += (int64_t)gridDim.x * kFilterThreads) {
+        const int64_t k = g / P, i = g - k * P;
+        normals(seed + (uint64_t)k, (uint32_t)i, 0u, D, z);
+        for (int d = 0; d < D; ++d) x[g * D + d] = (float)z[d];
     }
 }
 
 template <int DC>  // compile-time D (0 = runtime D)
 __global__ __launch_bounds__(kFilterThreads) void propagate_weight_kernel(
     const float *__restrict__ x_in, float *__restrict__ x_out, float *__restrict__ lw, int64_t P,
-    int Drt, const double *__restrict__ A, const float *__restrict__ y, double sq, double r,
-    double norm, uint64_t seed, uint32_t t)
+    int64_t K, int Drt, const double *__restrict__ A, const float *__restrict__ y, double sq,
+    const double *__restrict__ q_k, double r, double norm, uint64_t seed, uint32_t t)
 {
     const int D = DC > 0 ? DC : Drt;
     __shared__ double sA[kMaxD * kMaxD];
@@ -68,9 +74,11 @@ __global__ __launch_bounds__(kFilterThreads) void propagate_weight_kernel(
     __syncthreads();
     double z[DC > 0 ? DC : kMaxD];
     double xv[DC > 0 ? DC : kMaxD];
-    for (int64_t i = blockIdx.x * (int64_t)kFilterThreads + threadIdx.x; i < P;
-         i += (int64_t)gridDim.x * kFilterThreads) {
-        const float *xi = x_in + i * D;
+    for (int64_t g = blockIdx.x * (int64_t)kFilterThreads + threadIdx.x; g < K * P;
+         g += (int64_t)gridDim.x * kFilterThreads) {
+        const int64_t k = g / P, i = g - k * P;
+        const double sqk = q_k ? sqrt(q_k[k]) : sq;
+        const float *xi = x_in + g * D;
         if (DC > 0 && DC % 4 == 0) {
 #pragma unroll
             for (int q = 0; q < D / 4; ++q) {
@@ -80,18 +88,18 @@ __global__ __launch_bounds__(kFilterThreads) void propagate_weight_kernel(
         } else {
             for (int d = 0; d < D; ++d) xv[d] = (double)xi[d];
         }
-        normals(seed, (uint32_t)i, t, D, z);
+        normals(seed + (uint64_t)k, (uint32_t)i, t, D, z);
         double ss = 0.0;
         float out[DC > 0 ? DC : kMaxD];
         for (int a = 0; a < D; ++a) {
             double acc = 0.0;
             for (int b = 0; b < D; ++b) acc += sA[a * D + b] * xv[b];
-            const float xa = (float)(acc + sq * z[a]);
+            const float xa = (float)(acc + sqk * z[a]);
             out[a] = xa;
             const double e = sy[a] - (double)xa;
             ss += e * e;
         }
-        float *xo = x_out + i * D;
+        float *xo = x_out + g * D;
         if (DC > 0 && DC % 4 == 0) {
 #pragma unroll
             for (int q = 0; q < D / 4; ++q)
@@ -100,7 +108,7 @@ __global__ __launch_bounds__(kFilterThreads) void propagate_weight_kernel(
         } else {
             for (int d = 0; d < D; ++d) xo[d] = out[d];
         }
-        lw[i] = (float)(norm - 0.5 * ss / r);
+        lw[g] = (float)(norm - 0.5 * ss / r);
     }
 }
 
@@ -114,32 +122,34 @@ uint32_t filter_grid(int64_t P)
 
 }  // namespace
 
-int launch_filter_init(float *x, int64_t P, int32_t D, uint64_t seed, hipStream_t stream)
+int launch_filter_init(float *x, int64_t P, int64_t K, int32_t D, uint64_t seed,
+                       hipStream_t stream)
 {
-    hipLaunchKernelGGL(filter_init_kernel, dim3(filter_grid(P)), dim3(kFilterThreads), 0, stream,
-                       x, P, (int)D, seed);
+    hipLaunchKernelGGL(filter_init_kernel, dim3(filter_grid(K * P)), dim3(kFilterThreads), 0,
+                       stream, x, P, K, (int)D, seed);
     return launch_status();
 }
 
-int launch_filter_step(const float *x_in, float *x_out, float *lw, int64_t P, int32_t D,
-                       const double *A, const float *y, double q, double r, uint64_t seed,
-                       uint32_t t, hipStream_t stream)
+int launch_filter_step(const float *x_in, float *x_out, float *lw, int64_t P, int64_t K,
+                       int32_t D, const double *A, const float *y, double q, const double *q_k,
+                       double r, uint64_t seed, uint32_t t, hipStream_t stream)
 {
     const double log_two_pi = 1.8378770664093454835606594728112;
     const double norm = -0.5 * (double)D * (log_two_pi + log(r));
     const double sq = sqrt(q);
     const bool vec = ((((uintptr_t)x_in) | ((uintptr_t)x_out)) & 15) == 0;
-    const dim3 grid(filter_grid(P)), block(kFilterThreads);
+    const dim3 grid(filter_grid(K * P)), block(kFilterThreads);
+#define RS_FILTER_LAUNCH(DC)                                                                       \
+    hipLaunchKernelGGL(propagate_weight_kernel<DC>, grid, block, 0, stream, x_in, x_out, lw, P, K, \
+                       (int)D, A, y, sq, q_k, r, norm, seed, t)
     if (D == 8 && vec) {
-        hipLaunchKernelGGL(propagate_weight_kernel<8>, grid, block, 0, stream, x_in, x_out, lw, P,
-                           (int)D, A, y, sq, r, norm, seed, t);
+        RS_FILTER_LAUNCH(8);
     } else if (D == 4 && vec) {
-        hipLaunchKernelGGL(propagate_weight_kernel<4>, grid, block, 0, stream, x_in, x_out, lw, P,
-                           (int)D, A, y, sq, r, norm, seed, t);
+        RS_FILTER_LAUNCH(4);
     } else {
-        hipLaunchKernelGGL(propagate_weight_kernel<0>, grid, block, 0, stream, x_in, x_out, lw, P,
-                           (int)D, A, y, sq, r, norm, seed, t);
+        RS_FILTER_LAUNCH(0);
     }
+#undef RS_FILTER_LAUNCH
     return launch_status();
 }
 

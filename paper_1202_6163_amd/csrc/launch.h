@@ -110,14 +110,20 @@ struct BatchLaunch {
     int32_t blocks, unroll, chains_per_item;
     int64_t lds_max_p, max_table_tiles;
     size_t smem_main;
+    uint32_t instance_add;  // added to every instance's Philox instance word
 };
 
 int launch_batch(const BatchLaunch &launch, hipStream_t stream);
+int launch_batch_log_mean_weight(const BatchInstance *insts, int32_t n, double *acc,
+                                 hipStream_t stream);
 
-int launch_filter_init(float *x, int64_t P, int32_t D, uint64_t seed, hipStream_t stream);
+// K filters of P particles each (K = 1: one filter); q_k: per-filter
+// variances (device) or nullptr for the shared q.
+int launch_filter_init(float *x, int64_t P, int64_t K, int32_t D, uint64_t seed,
+                       hipStream_t stream);
 
-int launch_filter_step(const float *x_in, float *x_out, float *lw, int64_t P, int32_t D,
-                       const double *A, const float *y, double q, double r, uint64_t seed,
-                       uint32_t t, hipStream_t stream);
+int launch_filter_step(const float *x_in, float *x_out, float *lw, int64_t P, int64_t K,
+                       int32_t D, const double *A, const float *y, double q, const double *q_k,
+                       double r, uint64_t seed, uint32_t t, hipStream_t stream);
 
 }  // namespace rs

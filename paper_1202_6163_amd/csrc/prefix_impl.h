@@ -408,6 +408,7 @@ __device__ void table_body(int64_t P, uint64_t seed, uint32_t instance, char *ws
     if (sums.flags) {
         if (tid == 0 && part == 0) {
             h->flags = sums.flags;
+            h->lse = (sums.flags & (kFlagNan | kFlagPosInf)) ? (double)NAN : -(double)INFINITY;
             h->B = 0;
             if (B_used) *B_used = 0;
             if (lse_out)
