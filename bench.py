@@ -235,6 +235,7 @@ def main():
         out["dirichlet"] = dirichlet(torch, rs, workloads, args)
     if not args.no_filter:
         out["filter"] = filter_run(torch, workloads, args)
+        out["pmcmc"] = pmcmc_run(torch, workloads, args)
     if args.serve_seconds > 0:
         out["serving"] = serving(torch, args)
     if not args.no_cpu_baseline:
@@ -520,6 +521,59 @@ def filter_run(torch, workloads, args):
         res[resampler] = {"ms_per_run_p50": pct(ms, 50), "us_per_step": pct(ms, 50) * 1e3 / 200,
                           "loglik": f.loglik(lse)}
     return res
+
+
+def pmcmc_run(torch, workloads, args):
+    """Particle marginal Metropolis-Hastings over log q (Sec. 1's use of the
+    filter): K = 64 chains, each iteration K filters of P = 4096 particles,
+    D = 4, T = 100, run as one batch per time step; time per iteration
+    against K single-filter runs of the same size, and the posterior summary
+    against the Kalman grid posterior."""
+    import math
+    from oracle.kalman import kalman_loglik
+    from paper_1202_6163_amd.filter import BootstrapFilter
+    from paper_1202_6163_amd.pmcmc import BatchedFilters, pmmh
+    K, P, T = 64, 4096, 100
+    A = workloads.filter_model(D=4, seed=1)
+    y = workloads.filter_observations(A, T=T, q=0.1, r=0.5, seed=3)
+    yd = torch.from_numpy(y).cuda()
+    bf = BatchedFilters(A, K, P, r=0.5, seed=11)
+    bf.loglik(np.full(K, 0.1), yd, run=0)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n_eval = 5
+    for it in range(n_eval):
+        bf.loglik(np.full(K, 0.1), yd, run=1 + it)
+    batched_s = (time.perf_counter() - t0) / n_eval
+    single = BootstrapFilter(A, P, q=0.1, r=0.5, seed=11)
+    single.run(y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(8):
+        single.run(y)
+    single_s = (time.perf_counter() - t0) / 8 * K
+    grid = np.linspace(math.log(0.01), math.log(1.0), 241)
+    lp = np.array([kalman_loglik(A, y, math.exp(g), 0.5) for g in grid])
+    lp += -0.5 * ((grid - math.log(0.1)) / 1.0) ** 2
+    w = np.exp(lp - lp.max())
+    w /= w.sum()
+    pm = float((w * grid).sum())
+    psd = float(math.sqrt((w * (grid - pm) ** 2).sum()))
+    t0 = time.perf_counter()
+    iters = 60
+    chain, rate = pmmh(bf, yd, iters=iters, theta0=math.log(0.1), step=1.2 * psd, seed=4)
+    pmmh_s = time.perf_counter() - t0
+    samples = chain[20:].ravel()
+    return {"K": K, "P": P, "T": T, "D": 4,
+            "batched_s_per_iteration": batched_s, "single_filters_s_per_iteration": single_s,
+            "speedup": single_s / batched_s,
+            "filter_steps_per_s": K * T / batched_s,
+            "particle_steps_per_s": K * T * P / batched_s,
+            "pmmh_iterations": iters, "pmmh_seconds": pmmh_s, "acceptance": rate,
+            "posterior_mean_log_q": float(samples.mean()), "posterior_sd_log_q": float(samples.std()),
+            "grid_posterior_mean_log_q": pm, "grid_posterior_sd_log_q": psd,
+            "note": "eager launches (5 per time step for all K filters); single = "
+                    "BootstrapFilter.run per filter, eager"}
 
 
 def serving(torch, args):

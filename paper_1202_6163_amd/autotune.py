@@ -55,6 +55,7 @@ def tune_metropolis(torch, rs, points, candidates, reps=5):
             per[f"{P}:{B}"] = ms
             total += ms
         results.append((total, cand, per))
+        print(f"metropolis {cand}: {total:.3f} ms", file=sys.stderr, flush=True)
     results.sort(key=lambda r: r[0])
     return results
 
@@ -68,6 +69,7 @@ def tune_batch(torch, rs, instances, candidates, reps=5):
         b = Batch(instances, tuning=cand)
         g = G.capture(b.run)
         results.append((pct(G.replay_ms([g], reps), 50), cand))
+        print(f"batch {cand}: {results[-1][0]:.3f} ms", file=sys.stderr, flush=True)
     results.sort(key=lambda r: r[0])
     return results
 
