@@ -301,11 +301,19 @@ KERNEL_SOURCES = {
 
 
 def source_hash(kernel):
+    """Hash of the kernel family's sources, plus the stored launch tuning for
+    Metropolis (it selects the kernel variant that runs)."""
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1202_6163_amd", "csrc")
-    for name in sorted(KERNEL_SOURCES[kernel]):
-        with open(os.path.join(csrc, name), "rb") as f:
-            h.update(name.encode() + f.read())
+    pkg = os.path.join(ROOT, "paper_1202_6163_amd")
+    files = [os.path.join("csrc", name) for name in sorted(KERNEL_SOURCES[kernel])]
+    if kernel == "metropolis":
+        files.append("tuning.json")
+    for name in files:
+        try:
+            with open(os.path.join(pkg, name), "rb") as f:
+                h.update(name.encode() + f.read())
+        except OSError:
+            h.update(name.encode() + b"<missing>")
     return h.hexdigest()
 
 

@@ -23,7 +23,11 @@ TUNING_FILE = os.path.join(HERE, "tuning.json")
 
 
 def device_key(torch, lib):
-    return f"{torch.cuda.get_device_name(0)}|v{lib.rs_version()}"
+    """Architecture, compute-unit count and library version (the marketing
+    name is not stable: it depends on which device-name table a process finds)."""
+    props = torch.cuda.get_device_properties(0)
+    arch = getattr(props, "gcnArchName", "unknown").split(":")[0]
+    return f"{arch}|{props.multi_processor_count}cu|v{lib.rs_version()}"
 
 
 def load(torch, lib):

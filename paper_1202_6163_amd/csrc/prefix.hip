@@ -157,8 +157,9 @@ __global__ __launch_bounds__(kTileThreads) void cumulative_kernel(const float *_
         return;
     }
     const double Blo = t > 0 ? ws.bound[t - 1] : 0.0;
-    double Cv[4];
-    tile_cumulative(v, ws.h->m, Blo, ws.bound[t], Cs, Cv);
+    double w[4], Cv[4];
+    tile_weights(v, ws.h->m, w);
+    tile_cumulative(w, Blo, ws.bound[t], Cs, Cv);
     store_cumw(C, P, t, Cv);
     const int64_t Pp = part_size(P), S = sub_stride(P), ns = sub_per_part(P);
 #pragma unroll

@@ -457,14 +457,20 @@ __device__ void table_body(int64_t P, uint64_t seed, uint32_t instance, char *ws
 // In-tile cumulative weights C'_j from the thread's four log-weights v:
 // C'_j = min(Blo + L_j, Bhi), with L the zero-weight-aware running maximum of
 // the tile's scan, and C'_j = Bhi from the tile's last positive weight on.
-__device__ inline void tile_cumulative(const float v[4], float m, double Blo, double Bhi,
-                                       double *Cs, double Cout[4])
+__device__ __forceinline__ void tile_weights(const float v[4], float m, double w[4])
+{
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w[k] = exp((double)v[k] - (double)m);
+}
+
+// w: the thread's four weights exp(lw - m) (tile_weights), computed early by
+// callers that can overlap them with other waits.
+__device__ inline void tile_cumulative(const double w[4], double Blo, double Bhi, double *Cs,
+                                       double Cout[4])
 {
     __shared__ double red[kNW];
     __shared__ double sh_total;
-    double w[4], L[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) w[k] = exp((double)v[k] - (double)m);
+    double L[4];
     L[0] = w[0];
     L[1] = L[0] + w[1];
     L[2] = L[1] + w[2];
@@ -748,6 +754,9 @@ __device__ void fill_body(const float *__restrict__ lw, int32_t *__restrict__ an
         Blo = s_blo;
         Bhi = s_bhi;
     }
+    // the tile block's weights, while thread 0 settles the range
+    double wts[4];
+    if (tile_block) tile_weights(v, m, wts);
     if (threadIdx.x == 0) {
         int64_t ob = 0, oe = 0, a0 = 0;
         if (t >= 0) {
@@ -779,10 +788,13 @@ __device__ void fill_body(const float *__restrict__ lw, int32_t *__restrict__ an
     Bhi = sh_b[1];
     const bool want_off = off && tile_block;
     if (t < 0 || (ob >= oe && !(cumw && tile_block) && !want_off)) return;  // nothing to write
-    if (!tile_block) load_tile4(lw, P, t, v);
+    if (!tile_block) {
+        load_tile4(lw, P, t, v);
+        tile_weights(v, m, wts);
+    }
 
     double C[4];
-    tile_cumulative(v, m, Blo, Bhi, Cs, C);  // ends with a barrier
+    tile_cumulative(wts, Blo, Bhi, Cs, C);  // ends with a barrier
     if (cumw && tile_block) store_cumw(cumw, P, t, C);
 
     const bool keep = x_in || want_off;  // ancestors needed again from LDS
