@@ -183,6 +183,8 @@ def main():
         peak = VALU_SLOTS_PER_S / 1e12
         roofline = {"bound": "alu", "achieved": achieved, "peak": peak,
                     "unit": "TVALU-slot/s", "frac": achieved / peak, "traffic": traffic,
+                    "limiter": "random 4-byte L2 gathers of the proposed weights: see "
+                               "measured_ceilings (the VALU model prices Philox high)",
                     "kernel": "metropolis_kernel", "avg_launch_us": means["metropolis"] * 1e3,
                     "units_per_launch": {"chain_iterations": iters},
                     "algorithmic_per_unit": {"valu_slots": METRO_SLOTS_PER_ITER}}

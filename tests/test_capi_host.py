@@ -247,3 +247,28 @@ def test_resample_and_copy_arguments(L):
     assert call(kind=L.STRATIFIED, ws=None) == L.RS_EINVAL
     assert call(kind=L.STRATIFIED, wsb=8) == L.RS_EWORKSPACE
     assert call(kind=L.SYSTEMATIC, off=f(0x200008)) == L.RS_EINVAL  # off overlaps anc
+
+
+def test_batched_filter_and_batch_step_arguments(L):
+    lib = L.lib
+    f = ctypes.c_void_p
+    x, xo, lw, A, y, q = (f(0x100000), f(0x900000), f(0x1100000), f(0x1200000), f(0x1300000),
+                          f(0x1400000))
+    assert lib.filter_init_batch(None, 0, 10, 4, 1, None) == L.RS_OK      # K = 0: nothing to do
+    assert lib.filter_init_batch(None, 2, 10, 4, 1, None) == L.RS_EINVAL
+    assert lib.filter_init_batch(x, 2, 10, 65, 1, None) == L.RS_EINVAL    # D above 64
+    assert lib.filter_init_batch(x, -1, 10, 4, 1, None) == L.RS_EINVAL
+    ok = (x, xo, lw, 2, 10, 4, A, y, q, 0.5, 1, 1, None)
+    args = list(ok)
+    args[8] = None                                                      # q missing
+    assert lib.filter_propagate_weight_batch(*args) == L.RS_EINVAL
+    args = list(ok)
+    args[9] = 0.0                                                       # r must be > 0
+    assert lib.filter_propagate_weight_batch(*args) == L.RS_EINVAL
+    args = list(ok)
+    args[1] = f(0x100010)                                               # x_out overlaps x_in
+    assert lib.filter_propagate_weight_batch(*args) == L.RS_EINVAL
+    assert lib.resample_batch_at(None, 3, None) == L.RS_EINVAL
+    assert lib.rs_batch_log_mean_weight(None, f(0x1000), None) == L.RS_EINVAL
+    plan = L.BatchPlan()
+    assert lib.rs_batch_log_mean_weight(ctypes.byref(plan), f(0x1000), None) == L.RS_EINVAL
