@@ -218,7 +218,19 @@ int permute_copy(const int32_t *anc, const float *x_in, float *x_out, int64_t P,
  * log-likelihood each step). out [device] double[1].
  */
 int rs_log_sum_exp(const float *lw, int64_t P, double *out, void *ws, size_t ws_bytes,
-                   int32_t *status, hipStream_t stream); /* P >= 1 */
+                   int32_t *status, hipStream_t stream);
+/*
+ * The log sum_i exp(lw_i) that the last call on workspace ws computed, for
+ * P particles, in binary64 (the same bits rs_log_sum_exp gives): every
+ * prefix resampler (stratified, systematic, multinomial, also through
+ * resample_and_copy and resample_batch) and resample_metropolis_adaptive
+ * reduce the weights anyway, so a filter reads its likelihood factor here
+ * instead of reducing them twice. NaN (NaN or +inf weights) or -inf (all
+ * -inf) when that call flagged its input.
+ *   ws  [device] the workspace of that call, P its particle count
+ *   out [device] double[1]. Stream-ordered after that call; graph-capturable.
+ */
+int rs_workspace_log_sum_exp(const void *ws, int64_t P, double *out, hipStream_t stream); /* P >= 1 */
 
 /*
  * Batched resampling: many independent instances of uneven size in one graph

@@ -7,7 +7,7 @@ importing the package alone (e.g. for ``workloads``) needs no GPU library.
 """
 
 _API_NAMES = ("resample_metropolis", "resample_metropolis_adaptive", "resample_stratified", "resample_systematic",
-              "resample_multinomial", "resample_sorted", "resample_and_copy", "ancestors_to_offspring", "permute_copy", "rs_log_sum_exp",
+              "resample_multinomial", "resample_sorted", "resample_and_copy", "ancestors_to_offspring", "permute_copy", "rs_log_sum_exp", "rs_workspace_log_sum_exp",
               "metropolis_B", "rs_log_u_table", "rs_metropolis_set_tuning", "rs_metropolis_get_tuning",
               "workspace", "workspace_bytes", "RESAMPLERS")
 

@@ -81,6 +81,7 @@ def _load():
         "resample_and_copy": (ctypes.c_int, [ctypes.c_int, vp, vp, vp, i64, u32, u64, u32, vp, vp,
                                              ctypes.c_int32, vp, sz, i32p, vp]),
         "rs_sorted_workspace_bytes": (sz, [i64, ctypes.c_int]),
+        "rs_workspace_log_sum_exp": (ctypes.c_int, [vp, i64, vp, vp]),
         "resample_sorted": (ctypes.c_int, [ctypes.c_int, vp, vp, i64, u64, u32, vp, sz, i32p, vp]),
         "permute_copy": (ctypes.c_int, [vp, vp, vp, i64, ctypes.c_int32, i32p, vp]),
         "rs_log_sum_exp": (ctypes.c_int, [vp, i64, vp, vp, sz, i32p, vp]),

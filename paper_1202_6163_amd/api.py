@@ -180,6 +180,16 @@ def resample_and_copy(kind, lw, x_in, seed, instance=0, B=0, anc=None, off=None,
     return anc, x_out
 
 
+def rs_workspace_log_sum_exp(ws, P, out=None, stream=None):
+    """log sum exp(lw) computed by the last call on workspace ws (P particles)."""
+    _need(ws, torch.uint8, "ws")
+    out = torch.empty(1, dtype=torch.float64, device=ws.device) if out is None else out
+    _need(out, torch.float64, "out", 1)
+    check(lib.rs_workspace_log_sum_exp(_ptr(ws), int(P), _ptr(out), _stream_handle(stream)),
+          "rs_workspace_log_sum_exp")
+    return out
+
+
 def resample_sorted(kind, lw, seed, instance=0, anc=None, ws=None, status=None, stream=None):
     """Sorted-weight variant of resampler `kind` ("stratified", "systematic",
     "multinomial" or the RS code); returns the ancestors (original indices).

@@ -212,6 +212,12 @@ int resample_and_copy(int kind, const float *lw, int32_t *anc, int32_t *off, int
                                     stream, r));
 }
 
+int rs_workspace_log_sum_exp(const void *ws, int64_t P, double *out, hipStream_t stream)
+{
+    if (!ws || !out || P < 1 || P > kMaxP) return RS_EINVAL;
+    return map_rc(rs::launch_workspace_lse(ws, P, out, stream));
+}
+
 size_t rs_sorted_workspace_bytes(int64_t P, int kind)
 {
     if (P < 1 || (kind != RS_STRATIFIED && kind != RS_SYSTEMATIC && kind != RS_MULTINOMIAL))

@@ -52,6 +52,7 @@ int launch_prefix(int kind, const float *lw, int32_t *anc, int32_t *off, int64_t
 
 int launch_log_sum_exp(const float *lw, int64_t P, double *out, void *ws, int32_t *status,
                        hipStream_t stream);
+int launch_workspace_lse(const void *ws, int64_t P, double *out, hipStream_t stream);
 
 // Sorted-weight variant: workspace sections (byte offsets) and the launcher.
 // Returns 0, -2 (workspace too small for the sort) or -3.

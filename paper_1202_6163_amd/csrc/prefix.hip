@@ -404,6 +404,18 @@ int launch_prefix(int kind, const float *lw, int32_t *anc, int32_t *off, int64_t
     return launch_status();
 }
 
+__global__ void workspace_lse_kernel(const char *ws_raw, int64_t P, double *out)
+{
+    if (threadIdx.x == 0) *out = ws_view(const_cast<char *>(ws_raw), P).h->lse;
+}
+
+int launch_workspace_lse(const void *ws, int64_t P, double *out, hipStream_t stream)
+{
+    hipLaunchKernelGGL(workspace_lse_kernel, dim3(1), dim3(64), 0, stream,
+                       static_cast<const char *>(ws), P, out);
+    return launch_status();
+}
+
 int launch_adaptive_B(const float *lw, int64_t P, double eps, uint32_t B_max, void *ws,
                       uint32_t *B_used, int32_t *status, hipStream_t stream)
 {

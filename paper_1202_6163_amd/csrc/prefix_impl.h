@@ -686,7 +686,8 @@ __device__ void fill_body(const float *__restrict__ lw, int32_t *__restrict__ an
             h->m = m;
             h->W = W;
             h->delta = W / (double)P;
-            h->lse = flags ? (double)NAN : (double)m + log(W);
+            h->lse = flags ? ((flags & (kFlagNan | kFlagPosInf)) ? (double)NAN : -(double)INFINITY)
+                           : (double)m + log(W);
             if (flags) raise_flags(status, flags);
         }
     } else {

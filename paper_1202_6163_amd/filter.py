@@ -3,9 +3,11 @@
 The filter of Sec. 1 (initialisation, propagation, weighting, resampling)
 for the linear-Gaussian model x_t = A x_{t-1} + N(0, qI), y_t = x_t + N(0, rI),
 resampling at every step. Every step runs in the library's kernels: the
-propagate+weight kernel, the log-sum-exp reduction (the step's likelihood
-factor mean_i w_i = exp(lse - log P)), the chosen resampler and the ancestor
-copy. The whole run can be captured once into a HIP graph and replayed.
+propagate+weight kernel, the chosen resampler with the ancestor copy fused
+in, and the step's likelihood factor mean_i w_i = exp(lse - log P), read
+from the reduction the resampler performs anyway (a separate log-sum-exp
+only for the fixed-B Metropolis resampler, which never sums the weights).
+The whole run can be captured once into a HIP graph and replayed.
 """
 import math
 
@@ -38,18 +40,21 @@ class BootstrapFilter:
     def _step(self, t, y_t, lse_t):
         api.filter_propagate_weight(self.x, self.A, y_t, self.q, self.r, self.seed, t,
                                     x_out=self.xp, lw=self.lw)
-        api.rs_log_sum_exp(self.lw, out=lse_t, ws=self.ws, status=self.status)
         if self.resampler == "metropolis":
-            api.resample_metropolis(self.lw, self.B, self.seed, t, anc=self.anc,
-                                    status=self.status)
-        elif self.resampler == "metropolis_adaptive":
+            api.rs_log_sum_exp(self.lw, out=lse_t, ws=self.ws, status=self.status)
+            api.resample_and_copy("metropolis", self.lw, self.xp, self.seed, t, B=self.B,
+                                  anc=self.anc, x_out=self.x, status=self.status)
+            return
+        if self.resampler == "metropolis_adaptive":
             api.resample_metropolis_adaptive(self.lw, self.seed, t, eps=self.eps, B_max=self.B,
                                              anc=self.anc, B_used=self.B_used, ws=self.ws,
                                              status=self.status)
+            api.permute_copy(self.anc, self.xp, x_out=self.x, status=self.status)
         else:
-            fn = api.RESAMPLERS[self.resampler]
-            fn(self.lw, self.seed, t, anc=self.anc, ws=self.ws, status=self.status)
-        api.permute_copy(self.anc, self.xp, x_out=self.x, status=self.status)
+            # the resampler's own reduction gives the likelihood factor
+            api.resample_and_copy(self.resampler, self.lw, self.xp, self.seed, t, anc=self.anc,
+                                  x_out=self.x, ws=self.ws, status=self.status)
+        api.rs_workspace_log_sum_exp(self.ws, self.P, out=lse_t)
 
     def _run(self, y, lse):
         api.filter_init(self.x, self.seed)

@@ -504,3 +504,25 @@ def test_resample_and_copy_small_groups_and_flags(rs, kind):
         anc, xo = rs.resample_and_copy(kind, dev(bad), xb, 1, 0, status=st)
         assert int(host(st)[0]) == rs.FLAG_NAN
         assert np.array_equal(host(anc), np.arange(2000)) and torch.equal(xo, xb)
+
+
+# ----------------------------------------------------------------- log-sum-exp read back
+@pytest.mark.parametrize("kind", PREFIX)
+@pytest.mark.parametrize("P", [7, 3000, 100003])
+def test_workspace_log_sum_exp_equals_reduction(rs, kind, P):
+    lw = dev(workloads.normal_logweights(P, 2.0, 9))
+    ref = rs.rs_log_sum_exp(lw)
+    ws = rs.workspace(P, rs.MULTINOMIAL, lw.device)
+    getattr(rs, f"resample_{kind}")(lw, 1, 0, ws=ws)
+    got = rs.rs_workspace_log_sum_exp(ws, P)
+    assert torch.equal(got, ref)
+    x = dev(workloads.state_rows_exact(P, 4))
+    rs.resample_and_copy(kind, lw, x, 2, 0, ws=ws)
+    assert torch.equal(rs.rs_workspace_log_sum_exp(ws, P), ref)
+    for bad, want in ((np.nan, np.nan), (-np.inf, -np.inf)):
+        b = np.full(P, bad, dtype=np.float32) if bad == -np.inf else np.zeros(P, np.float32)
+        if bad != -np.inf:
+            b[P // 2] = bad
+        getattr(rs, f"resample_{kind}")(dev(b), 1, 0, ws=ws)
+        v = float(host(rs.rs_workspace_log_sum_exp(ws, P))[0])
+        assert (np.isnan(v) if np.isnan(want) else v == want), (bad, v)
