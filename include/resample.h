@@ -122,7 +122,7 @@ int resample_metropolis_adaptive(const float *lw, int32_t *anc, int64_t P, doubl
  * [i, i+1) * W / P of the cumulative weight, ancestor a_i = min{j : C_j > x_i}.
  * Ancestors come out sorted. The paper gives this resampler's output as
  * offspring counts; it writes ancestors, offspring or both in the same pass.
- * Multi-kernel: a tile reduction, a one-block table (more than 64 tiles),
+ * Multi-kernel: a tile reduction, a table launch (more than 64 tiles),
  * then a fused scan and fill.
  *   lw     [device] float[P]    log-weights
  *   anc    [device] int32[P]    ancestors (output, non-decreasing), nullable

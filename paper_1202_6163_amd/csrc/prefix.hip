@@ -12,18 +12,17 @@
 // Design on MI355X.
 //  1. tile_reduce_kernel streams lw once: per 1024-weight tile the max, the
 //     sum of exp(lw - tile max) in binary64 and the data flags.
-//  2. fill_kernel: every block rescales the tile sums to the global max and
-//     scans them into the tile boundaries B_t in LDS (a few KB: the same
-//     computation in every block costs less than another dependent launch),
-//     counts the draws below its tile's two boundaries (stratified/systematic
-//     draws are non-decreasing, so this is a short search near B / (W/P)),
-//     re-reads its tile of lw, rebuilds the tile's cumulative weights in LDS
-//     with a wave-level scan and locates each of its draws there, writing
-//     ancestors in order. Blocks beyond one per tile take the draws of heavy
-//     tiles by 2048-wide windows of draw index. Above 64 tiles a one-block
-//     table launch computes boundaries and counts once instead.
-//     With an offspring array each tile block also writes o_j for its tile's
-//     particles, counted from the sorted ancestors it holds in LDS.
+//  2. table_kernel (up to 8 blocks): the tile sums rescaled to the global
+//     max and scanned into the tile boundaries B_t, the number of draw points
+//     below each boundary (stratified/systematic draws are non-decreasing, so
+//     this is a short search near B / (W/P)) and the owners of the overflow
+//     windows. Up to 64 tiles the fill blocks do this themselves instead.
+//  3. fill_kernel: each block re-reads its tile of lw, rebuilds the tile's
+//     cumulative weights in LDS with a wave-level scan and locates each of
+//     its draws there, writing ancestors in order, and the tile's offspring
+//     o_j counted from the sorted ancestors it holds in LDS. Blocks beyond one
+//     per tile take the rest of heavy tiles by 2044-wide windows of draw
+//     index.
 // HBM traffic is two reads of lw and one write of anc (and/or off); the
 // cumulative weights are stored only on request. The multinomial draws are
 // unsorted, so that resampler stores C (launch 3m) and searches it per draw

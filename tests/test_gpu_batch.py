@@ -1,6 +1,8 @@
 """GPU batched resampling: every instance of a batch equals its single call
 bit for bit (ancestors and copied rows), under several tunings and across
 graph replays; a sample of instances also matches the oracle."""
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -128,3 +130,38 @@ def test_batch_full_workload_and_graph_replays(rs):
         torch.cuda.synchronize()
         for k, d in enumerate(insts):
             assert torch.equal(d["anc"], ref[k]), (rep, k)
+
+
+def test_batch_instance_offset_equals_single_calls(rs):
+    from paper_1202_6163_amd.batch import Batch
+    insts = make_instances(16, 6, 13, 4, seed=4)
+    b = Batch(insts)
+    add = 12345
+    b.run(instance_add=add)
+    torch.cuda.synchronize()
+    for k, d in enumerate(insts):
+        shifted = dict(d, instance=d["instance"] + add)
+        anc, out, off = single(rs, shifted)
+        assert torch.equal(d["anc"], anc), f"instance {k} ({d['kind']})"
+        if out is not None:
+            assert torch.equal(d["x_out"].view(torch.int32), out.view(torch.int32)), k
+        if off is not None:
+            assert torch.equal(d["off"], off), k
+
+
+def test_batch_log_mean_weight(rs):
+    from paper_1202_6163_amd.batch import Batch
+    insts = make_instances(10, 6, 13, 4, seed=6, with_copy=False)
+    b = Batch(insts)
+    b.run()
+    acc = torch.zeros(len(insts), dtype=torch.float64, device="cuda")
+    b.add_log_mean_weight(acc)
+    torch.cuda.synchronize()
+    for k, d in enumerate(insts):
+        P = d["lw"].numel()
+        if d["kind"] == "metropolis" or P == 0:
+            assert math.isnan(float(acc[k]))
+        else:
+            want = float(rs.rs_log_sum_exp(d["lw"])) - math.log(P)
+            # same lse bits; the device log(P) may differ from the host's in the last ulp
+            assert abs(float(acc[k]) - want) <= 1e-13 * max(1.0, abs(want)), k
