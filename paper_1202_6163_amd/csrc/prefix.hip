@@ -48,8 +48,8 @@ namespace {
 
 using namespace pfx;
 
-// Tables keep their per-tile arrays in LDS up to this many tiles.
-constexpr int64_t kTableLdsTiles = 4096;
+// Tables keep their boundaries in LDS up to this many tiles (128 KB).
+constexpr int64_t kTableLdsTiles = 16384;
 
 __global__ __launch_bounds__(kTileThreads) void tile_reduce_kernel(const float *__restrict__ lw,
                                                                    int64_t P, char *ws_raw)
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(kTileThreads) void table_kernel(int64_t P, uint64_t
                                                              double eps, uint32_t B_max,
                                                              uint32_t *B_used)
 {
-    extern __shared__ double sh_tab[];  // [n] boundaries, then [n] counts
+    extern __shared__ double sh_tab[];  // [n] boundaries, then the block's counts
     const WsView ws = ws_view(ws_raw, P);
     const int64_t n = num_tiles(P);
     double *bound = LDS ? sh_tab : ws.bound;
@@ -73,9 +73,9 @@ __global__ __launch_bounds__(kTileThreads) void table_kernel(int64_t P, uint64_t
                      blockIdx.x, gridDim.x);
 }
 
-// Stratified/systematic tables with LDS scratch split the counts over up to
-// kTableParts blocks (one tile per thread); the rest run one block.
-constexpr int kTableParts = 8;
+// Stratified/systematic tables with LDS boundaries split the counts over up
+// to kTableParts blocks; the rest run one block.
+constexpr int64_t kTableParts = 8;
 
 template <int KIND>
 void launch_table(int64_t P, uint64_t seed, uint32_t instance, char *w, int32_t *status,
@@ -84,11 +84,20 @@ void launch_table(int64_t P, uint64_t seed, uint32_t instance, char *w, int32_t 
 {
     const int64_t n = num_tiles(P);
     if (n <= kTableLdsTiles) {
-        const size_t smem = (size_t)n * (sizeof(double) + sizeof(int32_t));
         int64_t parts = 1;
         if (KIND == kStratified || KIND == kSystematic) {
             parts = (n + kTileThreads - 1) / kTileThreads;
             parts = parts > kTableParts ? kTableParts : parts;
+        }
+        const int64_t slice = (n + parts - 1) / parts + 2;  // a block's counts (one extra)
+        const size_t smem = (size_t)n * sizeof(double) + (size_t)slice * sizeof(int32_t);
+        static size_t granted = 0;  // dynamic LDS above the default needs the attribute
+        if (smem > granted) {
+            if (hipFuncSetAttribute(reinterpret_cast<const void *>(&table_kernel<KIND, true>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)smem) != hipSuccess)
+                return;
+            granted = smem;
         }
         hipLaunchKernelGGL((table_kernel<KIND, true>), dim3((uint32_t)parts), dim3(kTileThreads),
                            smem, stream, P, seed, instance, w, status, lse_out, eps, B_max,

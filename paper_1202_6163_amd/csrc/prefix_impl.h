@@ -299,10 +299,26 @@ __device__ inline TableSums boundaries(const WsView &ws, int64_t P, double *boun
 #pragma unroll
         for (int k = 0; k < kRegTiles; ++k) m = fmaxf(m, mt[k]);
     } else {
-        for (int64_t t = t0; t < t1; ++t) {
-            fl |= ws.tile_flags[t];
-            m = fmaxf(m, ws.tile_max[t]);
-            bound[t] = ws.tile_sum[t];
+        // longer runs: four tiles' loads in flight at a time
+        for (int64_t c = t0; c < t1; c += kRegTiles) {
+            float mc[kRegTiles];
+            double Sc[kRegTiles];
+            int fc[kRegTiles];
+#pragma unroll
+            for (int k = 0; k < kRegTiles; ++k) {
+                const bool in = c + k < t1;
+                mc[k] = in ? ws.tile_max[c + k] : -INFINITY;
+                Sc[k] = in ? ws.tile_sum[c + k] : 0.0;
+                fc[k] = in ? ws.tile_flags[c + k] : 0;
+            }
+#pragma unroll
+            for (int k = 0; k < kRegTiles; ++k) {
+                if (c + k < t1) {
+                    fl |= fc[k];
+                    m = fmaxf(m, mc[k]);
+                    bound[c + k] = Sc[k];
+                }
+            }
         }
     }
     // flags and max in one barrier (redi/redf are next written after later barriers)
@@ -332,11 +348,23 @@ __device__ inline TableSums boundaries(const WsView &ws, int64_t P, double *boun
             }
         }
     } else {
-        for (int64_t t = t0; t < t1; ++t) {
-            const float mtt = ws.tile_max[t];
-            const double St = (mtt > -INFINITY) ? bound[t] * exp((double)mtt - (double)m) : 0.0;
-            bound[t] = St;
-            local += St;
+        for (int64_t c = t0; c < t1; c += kRegTiles) {
+            float mc[kRegTiles];
+            double Sc[kRegTiles];
+#pragma unroll
+            for (int k = 0; k < kRegTiles; ++k) {
+                const bool in = c + k < t1;
+                mc[k] = in ? ws.tile_max[c + k] : -INFINITY;
+                Sc[k] = in ? bound[c + k] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < kRegTiles; ++k) {
+                if (c + k < t1) {
+                    const double St = (mc[k] > -INFINITY) ? Sc[k] * exp((double)mc[k] - (double)m) : 0.0;
+                    bound[c + k] = St;
+                    local += St;
+                }
+            }
         }
     }
     double run = block_exclusive_sum(local, redd);
@@ -381,11 +409,11 @@ __device__ inline TableSums boundaries(const WsView &ws, int64_t P, double *boun
 
 // The table launch: boundaries, and for stratified/systematic the draw
 // counts below every boundary and the owners of the overflow windows, into
-// the workspace. `bound` and `count` are scratch for n tiles (LDS when they
-// fit, else the workspace arrays). With parts > 1 (LDS scratch only) the
-// launch has that many blocks: each rebuilds all boundaries (the same bits)
-// and counts and publishes its own share of the tiles; block 0 writes the
-// header.
+// the workspace. `bound` is scratch for n tiles and `count` for the block's
+// tiles plus one (LDS when they fit, else the workspace arrays). With
+// parts > 1 (LDS boundaries only) the launch has that many blocks: each
+// rebuilds all boundaries (the same bits) and counts and publishes its own
+// share of the tiles; block 0 writes the header.
 //
 // Overflow windows: the draws of tile t beyond its fill block's slots,
 // [M_t, hi_t) with M_t = (lo_t & ~3) + kChunk, go to the kWindow-wide windows
@@ -424,15 +452,17 @@ __device__ void table_body(int64_t P, uint64_t seed, uint32_t instance, char *ws
         for (int64_t t = u0 + tid; t < u1; t += kTileThreads) ws.bound[t] = bound[t];
     if (KIND == kStratified || KIND == kSystematic) {
         const double u_sys = KIND == kSystematic ? systematic_offset(seed, instance) : 0.0;
-        // counts of tiles [u0 - 1, u1): the one before gives the first tile's lo
-        for (int64_t t = (u0 > 0 ? u0 - 1 : 0) + tid; t < u1; t += kTileThreads) {
+        // counts of tiles [c0, u1), c0 = u0 - 1 (that one gives the first tile's lo);
+        // count[t - c0] holds tile t's (the block's own slice of scratch)
+        const int64_t c0 = u0 > 0 ? u0 - 1 : 0;
+        for (int64_t t = c0 + tid; t < u1; t += kTileThreads) {
             const int32_t c = (int32_t)count_below<KIND>(bound[t], P, W, delta, seed, instance, u_sys);
-            count[t] = c;
-            if (staged && t >= u0) ws.count[t] = c;
+            count[t - c0] = c;
+            if (count != ws.count && t >= u0) ws.count[t] = c;
         }
         __syncthreads();
         for (int64_t t = u0 + tid; t < u1; t += kTileThreads) {
-            const int64_t lo = t > 0 ? count[t - 1] : 0, hi = count[t];
+            const int64_t lo = t > 0 ? count[t - 1 - c0] : 0, hi = count[t - c0];
             const int64_t M = (lo & ~(int64_t)3) + kChunk;
             for (int64_t q = (lo + kWindow - 1) / kWindow; q * kWindow < hi; ++q)
                 ws.win[q] = (M < hi && M < (q + 1) * kWindow) ? (int32_t)t : -1;
