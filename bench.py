@@ -210,6 +210,7 @@ def main():
                                  "bytes_per_particle": 20 + 8 * D},
     }
 
+    roofline_hbm["by_P"] = hbm_by_P(torch, rs, G, D)
     out = {
         "metric": "resampled particles/s at P=2^20 (Metropolis B vs stratified) by weight var; p99",
         "value": value, "unit": "particles/s", "n_gpus": 1, "steps": args.steps,
@@ -277,6 +278,40 @@ def ceilings(torch, rs, G, lw, metro_iter_per_s):
             "metropolis_iter_per_s": metro_iter_per_s, "iteration_ceiling_per_s": bound,
             "frac_of_measured_ceiling": metro_iter_per_s / bound,
             "gather_array_bytes": 4 * lw.numel(), "random_gather_per_s_by_array_bytes": by_size}
+
+
+def hbm_by_P(torch, rs, G, D):
+    """Stratified (ancestors + offspring) + state copy against HBM at growing P
+    (cold buffer sets): the fixed launch latency of the three dependent
+    launches is amortised as P grows."""
+    dev = torch.device("cuda", 0)
+    res = {}
+    for lg in (22, 24):
+        P = 1 << lg
+        nsets = 2 if lg >= 24 else 4
+        sets = [dict(lw=torch.randn(P, device=dev), x=torch.randn(P, D, device=dev),
+                     xo=torch.empty(P, D, device=dev),
+                     anc=torch.empty(P, dtype=torch.int32, device=dev),
+                     off=torch.empty(P, dtype=torch.int32, device=dev)) for _ in range(nsets)]
+        ws = rs.workspace(P, rs.MULTINOMIAL, dev)
+
+        def body(copy):
+            for k, bs in enumerate(sets):
+                rs.resample_stratified(bs["lw"], k, 0, anc=bs["anc"], ws=ws, off=bs["off"])
+                if copy:
+                    rs.permute_copy(bs["anc"], bs["x"], x_out=bs["xo"])
+        entry = {}
+        for name, copy, bpp in (("stratified", False, 16), ("stratified_plus_copy", True, 20 + 8 * D)):
+            g = G.capture(lambda copy=copy: body(copy))
+            G.replay_ms([g], 2)
+            us = float(np.median(G.replay_ms([g], 6))) * 1e3 / nsets
+            gbs = bpp * P / (us * 1e-6) / 1e9
+            entry[name] = {"us": us, "achieved": gbs, "frac": gbs / HBM_PEAK_GBS,
+                           "bytes_per_particle": bpp}
+        res[f"2^{lg}"] = entry
+        del sets
+        torch.cuda.empty_cache()
+    return res
 
 
 def load_traffic(kernel):
