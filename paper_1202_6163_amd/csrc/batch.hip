@@ -165,14 +165,8 @@ int launch_batch(const BatchLaunch &L, hipStream_t stream)
         const dim3 grid(grid_of(L.n_main_items, L.blocks)), block(kThreads);
 #define RS_BATCH_CASE(U)                                                                         \
     case U: {                                                                                    \
-        static size_t granted = 0;                                                               \
-        if (smem > granted) {                                                                    \
-            if (hipFuncSetAttribute(reinterpret_cast<const void *>(&batch_main_kernel<U>),       \
-                                    hipFuncAttributeMaxDynamicSharedMemorySize,                  \
-                                    (int)smem) != hipSuccess)                                    \
-                return launch_status();                                                          \
-            granted = smem;                                                                      \
-        }                                                                                        \
+        if (allow_dynamic_lds(reinterpret_cast<const void *>(&batch_main_kernel<U>), smem))     \
+            return -3;                                                                           \
         hipLaunchKernelGGL(batch_main_kernel<U>, grid, block, smem, stream, L.insts, L.main_items, \
                            L.n_main_items, L.chains_per_item, L.lds_max_p, L.instance_add);      \
         break;                                                                                   \

@@ -5,7 +5,9 @@
 
 #include <cmath>
 #include <cstdlib>
+#include <map>
 #include <mutex>
+#include <utility>
 
 #include "analysis.h"
 #include "launch.h"
@@ -24,6 +26,22 @@ int record_hip_error(hipError_t e)
     return -3;
 }
 int launch_status() { return record_hip_error(hipGetLastError()); }
+
+int allow_dynamic_lds(const void *fn, size_t bytes)
+{
+    static std::mutex mu;
+    static std::map<std::pair<int, const void *>, size_t> granted;  // (device, kernel) -> bytes
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return record_hip_error(e);
+    std::lock_guard<std::mutex> lock(mu);
+    size_t &have = granted[{dev, fn}];
+    if (bytes <= have) return 0;
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return record_hip_error(e);
+    have = bytes;
+    return 0;
+}
 }  // namespace rs
 
 namespace {

@@ -13,6 +13,11 @@ namespace rs {
 int launch_status();
 int record_hip_error(hipError_t e);
 
+// Lets kernel `fn` launch with `bytes` of dynamic LDS on the current device
+// (raises the kernel's limit once per device and size; thread-safe).
+// Returns 0 or -3.
+int allow_dynamic_lds(const void *fn, size_t bytes);
+
 // Particle state rows to copy with the ancestors (x_out[i, :] = x_in[a_i, :]),
 // D binary32 values per row; x_in == nullptr: no copy.
 struct Rows {

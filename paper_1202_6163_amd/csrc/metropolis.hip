@@ -109,14 +109,9 @@ int launch_variant(const float *lw, int32_t *anc, uint32_t P, uint32_t B, uint64
     size_t smem = 0;
     if (STAGE) {
         smem = (size_t)P * sizeof(float);
-        static size_t granted = 0;  // dynamic LDS granted to this kernel so far
-        if (smem > granted) {
-            if (hipFuncSetAttribute(reinterpret_cast<const void *>(&metropolis_kernel<UNROLL, STAGE>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)smem) != hipSuccess)
-                return launch_status();
-            granted = smem;
-        }
+        if (allow_dynamic_lds(reinterpret_cast<const void *>(&metropolis_kernel<UNROLL, STAGE>),
+                              smem))
+            return -3;
     }
     hipLaunchKernelGGL((metropolis_kernel<UNROLL, STAGE>), dim3((uint32_t)grid), dim3(block),
                        smem, stream, lw, anc, P, B, seed, instance, lpc_log2, status, B_dev, rows);

@@ -78,7 +78,7 @@ __global__ __launch_bounds__(kTileThreads) void table_kernel(int64_t P, uint64_t
 constexpr int64_t kTableParts = 8;
 
 template <int KIND>
-void launch_table(int64_t P, uint64_t seed, uint32_t instance, char *w, int32_t *status,
+int launch_table(int64_t P, uint64_t seed, uint32_t instance, char *w, int32_t *status,
                   double *lse_out, hipStream_t stream, double eps = 0.0, uint32_t B_max = 0,
                   uint32_t *B_used = nullptr)
 {
@@ -91,14 +91,8 @@ void launch_table(int64_t P, uint64_t seed, uint32_t instance, char *w, int32_t 
         }
         const int64_t slice = (n + parts - 1) / parts + 2;  // a block's counts (one extra)
         const size_t smem = (size_t)n * sizeof(double) + (size_t)slice * sizeof(int32_t);
-        static size_t granted = 0;  // dynamic LDS above the default needs the attribute
-        if (smem > granted) {
-            if (hipFuncSetAttribute(reinterpret_cast<const void *>(&table_kernel<KIND, true>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)smem) != hipSuccess)
-                return;
-            granted = smem;
-        }
+        if (allow_dynamic_lds(reinterpret_cast<const void *>(&table_kernel<KIND, true>), smem))
+            return -3;
         hipLaunchKernelGGL((table_kernel<KIND, true>), dim3((uint32_t)parts), dim3(kTileThreads),
                            smem, stream, P, seed, instance, w, status, lse_out, eps, B_max,
                            B_used);
@@ -106,6 +100,7 @@ void launch_table(int64_t P, uint64_t seed, uint32_t instance, char *w, int32_t 
         hipLaunchKernelGGL((table_kernel<KIND, false>), dim3(1), dim3(kTileThreads), 0, stream, P,
                            seed, instance, w, status, lse_out, eps, B_max, B_used);
     }
+    return 0;
 }
 
 template <int KIND, bool FUSED>
@@ -128,7 +123,7 @@ __global__ __launch_bounds__(kTileThreads) void fill_kernel(const float *__restr
 // launch computes them once (three launches). Same values either way: both
 // run pfx::boundaries and pfx::count_below.
 template <int KIND>
-void launch_fill(const float *lw, int32_t *anc, int32_t *off, int64_t P, uint64_t seed,
+int launch_fill(const float *lw, int32_t *anc, int32_t *off, int64_t P, uint64_t seed,
                  uint32_t instance, double *cumw, char *w, int32_t *status, hipStream_t stream,
                  const Rows &rows)
 {
@@ -138,10 +133,11 @@ void launch_fill(const float *lw, int32_t *anc, int32_t *off, int64_t P, uint64_
         hipLaunchKernelGGL((fill_kernel<KIND, true>), grid, tb, (size_t)n * sizeof(double), stream,
                            lw, anc, off, P, seed, instance, cumw, w, status, rows);
     } else {
-        launch_table<KIND>(P, seed, instance, w, status, nullptr, stream);
+        if (const int rc = launch_table<KIND>(P, seed, instance, w, status, nullptr, stream)) return rc;
         hipLaunchKernelGGL((fill_kernel<KIND, false>), grid, tb, 0, stream, lw, anc, off, P, seed,
                            instance, cumw, w, status, rows);
     }
+    return 0;
 }
 
 // ------------------------------------------------------ multinomial
@@ -379,25 +375,24 @@ int launch_prefix(int kind, const float *lw, int32_t *anc, int32_t *off, int64_t
     hipLaunchKernelGGL(tile_reduce_kernel, dim3((uint32_t)n), tb, 0, stream, lw, P, w);
     switch (kind) {
     case kStratified:
-        launch_fill<kStratified>(lw, anc, off, P, seed, instance, cumw, w, status, stream, rows);
+        if (const int rc = launch_fill<kStratified>(lw, anc, off, P, seed, instance, cumw, w, status,
+                                                    stream, rows))
+            return rc;
         break;
     case kSystematic:
-        launch_fill<kSystematic>(lw, anc, off, P, seed, instance, cumw, w, status, stream, rows);
+        if (const int rc = launch_fill<kSystematic>(lw, anc, off, P, seed, instance, cumw, w, status,
+                                                    stream, rows))
+            return rc;
         break;
     case kMultinomial: {
         double *C = cumw ? cumw : reinterpret_cast<double *>(w + ws_layout(P, true).cumw);
-        launch_table<kMultinomial>(P, seed, instance, w, status, nullptr, stream);
+        if (const int rc = launch_table<kMultinomial>(P, seed, instance, w, status, nullptr, stream))
+            return rc;
         hipLaunchKernelGGL(cumulative_kernel, dim3((uint32_t)n), tb, 0, stream, lw, P, C, w, seed,
                            instance);
         const size_t smem = (size_t)sub_per_part(P) * sizeof(double);
-        static size_t granted = 0;  // dynamic LDS above the default needs the attribute
-        if (smem > granted) {
-            if (hipFuncSetAttribute(reinterpret_cast<const void *>(&multinomial_search_kernel),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)smem) != hipSuccess)
-                return launch_status();
-            granted = smem;
-        }
+        if (allow_dynamic_lds(reinterpret_cast<const void *>(&multinomial_search_kernel), smem))
+            return -3;
         // K blocks per part: one per CU of an XCD at most, a chunk each at least
         int64_t K = (P + kQueue - 1) / kQueue;
         K = K < 1 ? 1 : (K > 32 ? 32 : K);
@@ -430,7 +425,9 @@ int launch_adaptive_B(const float *lw, int64_t P, double eps, uint32_t B_max, vo
     char *w = static_cast<char *>(ws);
     hipLaunchKernelGGL(tile_reduce_kernel, dim3((uint32_t)num_tiles(P)), dim3(kTileThreads), 0,
                        stream, lw, P, w);
-    launch_table<kAdaptiveB>(P, 0, 0u, w, status, nullptr, stream, eps, B_max, B_used);
+    if (const int rc = launch_table<kAdaptiveB>(P, 0, 0u, w, status, nullptr, stream, eps, B_max,
+                                                B_used))
+        return rc;
     return launch_status();
 }
 
@@ -445,7 +442,7 @@ int launch_log_sum_exp(const float *lw, int64_t P, double *out, void *ws, int32_
     char *w = static_cast<char *>(ws);
     hipLaunchKernelGGL(tile_reduce_kernel, dim3((uint32_t)num_tiles(P)), dim3(kTileThreads), 0,
                        stream, lw, P, w);
-    launch_table<kLogSumExp>(P, 0, 0u, w, status, out, stream);
+    if (const int rc = launch_table<kLogSumExp>(P, 0, 0u, w, status, out, stream)) return rc;
     return launch_status();
 }
 
