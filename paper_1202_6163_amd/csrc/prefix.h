@@ -41,7 +41,7 @@ struct alignas(64) WsHeader {
 };
 
 struct WsLayout {
-    size_t header, tile_max, tile_sum, tile_flags, bound, count, win, sub, part, cumw, total;
+    size_t header, tile_max, tile_sum, tile_flags, bound, count, win, sub, guide, part, cumw, total;
 };
 
 __host__ __device__ inline size_t ws_align(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -77,6 +77,9 @@ __host__ __device__ inline int64_t sub_per_part(int64_t P)
     return (part_size(P) + s - 1) / s;
 }
 __host__ __device__ inline int64_t num_sub(int64_t P) { return kParts * sub_per_part(P); }
+// The search's guide table per part: entries 0 .. sub_per_part(P) (uint16),
+// padded to whole 16-byte vectors.
+__host__ __device__ inline int64_t guide_stride(int64_t P) { return (sub_per_part(P) + 8) / 8 * 8; }
 
 __host__ __device__ inline WsLayout ws_layout(int64_t P, bool with_cumw)
 {
@@ -89,10 +92,11 @@ __host__ __device__ inline WsLayout ws_layout(int64_t P, bool with_cumw)
     L.bound = L.tile_flags + ws_align(n * sizeof(int32_t));
     L.count = L.bound + ws_align(n * sizeof(double));
     L.win = L.count + ws_align(n * sizeof(int32_t));
-    // the multinomial sections (group ends, draw parts, C) sit past the shared
+    // the multinomial sections (group ends, guide, draw parts, C) sit past the shared
     // ones at the same offsets whatever the kind; only the size differs
     L.sub = L.win + ws_align((size_t)num_windows(P) * sizeof(int32_t));
-    L.part = L.sub + ws_align((size_t)num_sub(P) * sizeof(double));
+    L.guide = L.sub + ws_align((size_t)num_sub(P) * sizeof(double));
+    L.part = L.guide + ws_align((size_t)(kParts * guide_stride(P)) * sizeof(uint16_t));
     L.cumw = L.part + ws_align((size_t)P + 16);
     L.total = with_cumw ? L.cumw + ws_align((size_t)P * sizeof(double)) : L.sub;
     return L;

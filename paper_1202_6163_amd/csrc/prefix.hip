@@ -140,6 +140,57 @@ int launch_fill(const float *lw, int32_t *anc, int32_t *off, int64_t P, uint64_t
     return 0;
 }
 
+// Guide table of the multinomial search (Chen and Asau's method for
+// inverse-CDF sampling). Part x's C' range [lo, hi] (lo = C' before the part,
+// hi = its last C', both tile boundaries) is cut into nb = groups equal
+// buckets; bucket(v) = floor((v - lo) nb / (hi - lo)) clamped to [0, nb).
+// Each step is monotone in v (rounded subtraction, product by a non-negative
+// scale, clamp), so v <= v' gives bucket(v) <= bucket(v'): the guide's
+// bounds below rest on that, not on the buckets being exactly equal. Every
+// kernel derives the buckets from the same bound entries, bit for bit.
+struct Buckets {
+    double base, scale;
+    int nb;
+    __device__ __forceinline__ int of(double v) const
+    {
+        const double f = (v - base) * scale;
+        return f >= (double)nb ? nb - 1 : (f > 0.0 ? (int)f : 0);
+    }
+};
+
+// Part x's bounds in C': lo = C' before its first particle, hi = its last C'.
+__device__ __forceinline__ void part_range(const double *bound, int64_t P, int part, double *lo,
+                                           double *hi)
+{
+    const int64_t Pp = part_size(P), start = part * Pp, end = min(start + Pp, P);
+    *lo = start > 0 ? bound[start / kTile - 1] : 0.0;
+    *hi = bound[(end - 1) / kTile];
+}
+
+__device__ __forceinline__ Buckets make_buckets(double lo, double hi, int nb)
+{
+    Buckets bk;
+    bk.nb = nb;
+    bk.base = lo;
+    const double width = hi - lo;
+    double scale = (width > 0.0 && width < (double)INFINITY) ? (double)nb / width : 0.0;
+    if (!(scale < (double)INFINITY)) scale = 0.0;
+    bk.scale = scale;
+    return bk;
+}
+
+// guide[q] = v for q in [from, to), 16-byte stores where aligned (a group
+// holding much of the part's weight spans many buckets).
+__device__ __forceinline__ void fill_guide(uint16_t *guide, int from, int to, uint16_t v)
+{
+    int q = from;
+    for (; q < to && (q & 7); ++q) guide[q] = v;
+    const uint32_t v2 = (uint32_t)v * 0x10001u;
+    const uint4 v8 = make_uint4(v2, v2, v2, v2);
+    for (; q + 8 <= to; q += 8) *reinterpret_cast<uint4 *>(guide + q) = v8;
+    for (; q < to; ++q) guide[q] = v;
+}
+
 // ------------------------------------------------------ multinomial
 // Launch 3m: one block per tile writes C' for the tile, and into ws.sub the
 // last C' of every sub_stride(P)-particle group of each part (the last group
@@ -166,12 +217,34 @@ __global__ __launch_bounds__(kTileThreads) void cumulative_kernel(const float *_
     tile_cumulative(w, Blo, ws.bound[t], Cs, Cv);
     store_cumw(C, P, t, Cv);
     const int64_t Pp = part_size(P), S = sub_stride(P), ns = sub_per_part(P);
+    // the group ends of this tile, and their guide entries: group g writes
+    // guide[q] = g for the buckets q in (bucket(end[g - 1]), bucket(end[g])],
+    // the part's last group also (bucket(end[last]), nb]; so guide[q] is the
+    // first group whose end lies in bucket q or later and every entry is
+    // written once. A group's predecessor end is in this tile's Cs or is an
+    // earlier tile's last C', which equals that tile's bound bit for bit.
+    const int xt = (int)(t * kTile / Pp);  // a part is whole tiles
+    double plo, phi;
+    part_range(ws.bound, P, xt, &plo, &phi);
+    const Buckets bk = make_buckets(plo, phi, (int)((min((xt + 1) * Pp, P) - xt * Pp + S - 1) / S));
+    uint16_t *guide = ws.guide + xt * guide_stride(P);
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
         const int64_t e = t * kTile + 4 * (int64_t)threadIdx.x + m;
         if (e >= P) break;
-        const int64_t x = e / Pp, local = e - x * Pp, end = min((x + 1) * Pp, P);
-        if ((local + 1) % S == 0 || e == end - 1) ws.sub[x * ns + local / S] = Cv[m];
+        const int64_t local = e - xt * Pp, end = min((xt + 1) * Pp, P);
+        if ((local + 1) % S == 0 || e == end - 1) {
+            const int64_t g = local / S;
+            ws.sub[xt * ns + g] = Cv[m];
+            const int bg = bk.of(Cv[m]);
+            int bp = -1;
+            if (g > 0) {
+                const int64_t pe = xt * Pp + g * S - 1;
+                bp = bk.of(pe >= t * kTile ? Cs[pe - t * kTile] : ws.bound[pe / kTile]);
+            }
+            if (bg > bp) fill_guide(guide, bp + 1, bg + 1, (uint16_t)g);
+            if (e == end - 1) fill_guide(guide, max(bg, bp) + 1, bk.nb + 1, (uint16_t)g);
+        }
     }
     // The part of each of the tile's draws [t kTile, (t+1) kTile) (two Philox
     // blocks per thread): part y holds C' in [B_{y Pp / kTile - 1}, the next
@@ -216,14 +289,20 @@ __device__ __forceinline__ int64_t first_above(const double *a, int64_t len, dou
 // Launch 4m: kParts x K blocks of 1024 threads; blocks b = x, x + kParts, ...
 // serve part x (the draws whose ancestor lies in it), so with the round-robin
 // placement of blocks on the XCDs one XCD searches one part and its slice of
-// C stays in that XCD's L2. A block scans the part bytes of its share of the
-// draws in chunks (16 per thread), queues the draws of its part in LDS
-// (wave-aggregated slots), then every thread takes queued draws, redraws x,
-// bisects the part's group ends staged in LDS and reads the group's 16 C'
-// (one 128-byte line, up to 2^20 particles) with eight 16-byte loads.
+// C stays in that XCD's L2. A block stages the part's group ends (every S-th
+// C') in LDS and builds a guide table over them (Chen and Asau's method for
+// inverse-CDF sampling): the part's C' range is cut into as many equal buckets
+// as there are groups, and guide[b] is the first group whose end falls in
+// bucket b or later. It then scans the part bytes of its share of the draws in
+// chunks (16 per thread), queues the draws of its part in LDS (wave-aggregated
+// slots), and every thread takes queued draws, redraws x, bisects only the
+// groups [guide[b], guide[b + 1]] of x's bucket (about one on average) and
+// counts the group's 16 C' (one 128-byte line, up to 2^20 particles), eight
+// lanes reading each line together.
 constexpr int kSearchThreads = 1024;
 constexpr int kIdsPerThread = 16;
 constexpr int kQueue = kSearchThreads * kIdsPerThread;
+constexpr int kSlots = 3;
 
 __device__ __forceinline__ double multinomial_draw(uint64_t seed, uint32_t instance, int64_t i,
                                                    double W, double capW)
@@ -245,12 +324,52 @@ __device__ __forceinline__ int first_above_lds(const double *a, int n, double x)
     return base;
 }
 
+// The 16 part bytes of draws [i0, i0 + 16), read unconditionally (from the
+// array's start when i0 >= d1: the caller ignores bytes past d1), so the load
+// stays in flight instead of being waited on at the end of a branch.
+__device__ __forceinline__ uint4 load_part_bytes(const uint8_t *part, int64_t i0, int64_t d1)
+{
+    return *reinterpret_cast<const uint4 *>(part + (i0 < d1 ? i0 : 0));
+}
+
+// For each lane's draw (x, gbase) with coop set: the number of the 16 C' of
+// its group (one 128-byte line at C + gbase) that are <= x. Eight lanes read
+// a line together, 16 bytes each, so one load instruction covers eight whole
+// lines (the address unit then handles 8 lines per instruction, not 64); a
+// ballot per comparison gives each owner its line's count. Every lane of the
+// wave must call this (lanes without a draw pass coop = false).
+__device__ __forceinline__ int line_count_coop(const double *C, double x, int64_t gbase, bool coop)
+{
+    const int lane = lane_id(), grp = lane >> 3, sub = lane & 7;
+    double2 c[8];
+    double xs[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int src = 8 * r + grp;  // the owner of the draw this group reads
+        xs[r] = __shfl(x, src, kWave);
+        const int64_t gs = __shfl(gbase, src, kWave);
+        const bool cs = __shfl((int)coop, src, kWave) != 0;
+        c[r] = cs ? reinterpret_cast<const double2 *>(C + gs)[sub]
+                  : make_double2((double)INFINITY, (double)INFINITY);
+    }
+    int cnt = 0;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const uint64_t m1 = __ballot(c[r].x <= xs[r]), m2 = __ballot(c[r].y <= xs[r]);
+        if (grp == r)  // this lane owns the draw read by group sub in round r
+            cnt = __popcll((m1 >> (8 * sub)) & 0xffull) + __popcll((m2 >> (8 * sub)) & 0xffull);
+    }
+    return cnt;
+}
+
 __global__ __launch_bounds__(kSearchThreads) void multinomial_search_kernel(
     const double *__restrict__ C, int32_t *__restrict__ anc, int64_t P, uint64_t seed,
     uint32_t instance, char *ws_raw, Rows rows)
 {
     extern __shared__ double sh_sub[];
     __shared__ int32_t sh_queue[kQueue];
+    __shared__ __align__(16) uint16_t sh_guide[kSubMax + 8];
+    static_assert(kSubMax % 8 == 0, "guide rows are whole 16-byte vectors");
     __shared__ int32_t sh_count[2];
     const WsView ws = ws_view(ws_raw, P);
     const int part = (int)(blockIdx.x % kParts);
@@ -260,7 +379,30 @@ __global__ __launch_bounds__(kSearchThreads) void multinomial_search_kernel(
     // this block's draws [d0, d1), a multiple of 16 wide
     const int64_t span = ((P + K - 1) / K + kIdsPerThread - 1) / kIdsPerThread * kIdsPerThread;
     const int64_t d0 = min(P, rank * span), d1 = min(P, d0 + span);
+    // every global read of the set-up is issued before the first wait: the
+    // header, the first chunk's part bytes, the group ends (at most kSubMax,
+    // 8 per thread) and the guide
     const int flags = ws.h->flags;
+    const double W = ws.h->W, capW = below(W);
+    const int groups = start < P ? (int)((end - start + S - 1) / S) : 0;
+    double plo = 0.0, phi = 0.0;
+    if (start < P) part_range(ws.bound, P, part, &plo, &phi);
+    uint4 pv = load_part_bytes(ws.part, d0 + (int64_t)kIdsPerThread * threadIdx.x, d1);
+    constexpr int kStage = (int)(kSubMax / kSearchThreads);
+    static_assert(kSubMax % kSearchThreads == 0, "whole staging rounds");
+    double stage[kStage];
+#pragma unroll
+    for (int r = 0; r < kStage; ++r) {
+        const int k = (int)threadIdx.x + r * kSearchThreads;
+        stage[r] = k < groups ? ws.sub[part * ns + k] : 0.0;
+    }
+    // the part's guide: at most kSubMax + 8 entries, 16 bytes per thread and
+    // one more vector for thread 0
+    const int gv = start < P ? (int)(guide_stride(P) / 8) : 0;
+    const uint4 *gsrc = reinterpret_cast<const uint4 *>(ws.guide + part * guide_stride(P));
+    const uint4 g0v = (int)threadIdx.x < gv ? gsrc[threadIdx.x] : make_uint4(0u, 0u, 0u, 0u);
+    const uint4 g1v = threadIdx.x == 0 && gv > kSearchThreads ? gsrc[kSearchThreads]
+                                                            : make_uint4(0u, 0u, 0u, 0u);
     if (flags) {  // identity, written by the blocks of part 0
         if (part == 0) {
             for (int64_t i = d0 + threadIdx.x; i < d1; i += kSearchThreads) {
@@ -271,29 +413,35 @@ __global__ __launch_bounds__(kSearchThreads) void multinomial_search_kernel(
         return;
     }
     if (start >= P) return;  // fewer tiles than parts
-    const int groups = (int)((end - start + S - 1) / S);
-    for (int k = threadIdx.x; k < groups; k += kSearchThreads) sh_sub[k] = ws.sub[part * ns + k];
+#pragma unroll
+    for (int r = 0; r < kStage; ++r) {
+        const int k = (int)threadIdx.x + r * kSearchThreads;
+        if (k < groups) sh_sub[k] = stage[r];
+    }
+    if ((int)threadIdx.x < gv) reinterpret_cast<uint4 *>(sh_guide)[threadIdx.x] = g0v;
+    if (threadIdx.x == 0 && gv > kSearchThreads)
+        reinterpret_cast<uint4 *>(sh_guide)[kSearchThreads] = g1v;
     if (threadIdx.x == 0) {
         sh_count[0] = 0;
         sh_count[1] = 0;
     }
-    const double W = ws.h->W, capW = below(W);
     const bool vec = S == 16 && (((uintptr_t)C) & 15) == 0;
     __syncthreads();
+    const Buckets bk = make_buckets(plo, phi, groups);
     const int lane = lane_id();
     int parity = 0;
     for (int64_t c0 = d0; c0 < d1; c0 += kQueue) {
         // (1) this thread's 16 part bytes; bit b of keep marks draw i0 + b as ours
         const int64_t i0 = c0 + (int64_t)kIdsPerThread * threadIdx.x;
         uint32_t keep = 0;
-        if (i0 < d1) {
-            const uint4 v = *reinterpret_cast<const uint4 *>(ws.part + i0);
-            const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+        {
+            const uint32_t w4[4] = {pv.x, pv.y, pv.z, pv.w};
 #pragma unroll
             for (int b = 0; b < kIdsPerThread; ++b)
                 if (i0 + b < d1 && ((w4[b >> 2] >> (8 * (b & 3))) & 0xffu) == (uint32_t)part)
                     keep |= 1u << b;
         }
+        pv = load_part_bytes(ws.part, i0 + kQueue, d1);  // the next chunk's, while this one runs
         // (2) queue slots: a wave-wide prefix of the counts, one LDS atomic per wave
         const int cnt = __popc(keep);
         int incl = cnt;
@@ -314,43 +462,39 @@ __global__ __launch_bounds__(kSearchThreads) void multinomial_search_kernel(
         __syncthreads();
         const int n = sh_count[parity];
         if (threadIdx.x == 0) sh_count[parity ^ 1] = 0;  // the next chunk's counter
-        // (3) search the queued draws, two per thread at a time
-        for (int idx = threadIdx.x; idx < n; idx += 2 * kSearchThreads) {
-            int64_t i[2], j[2];
-            bool on[2];
+        // (3) search the queued draws, up to kSlots per thread at a time (a
+        // chunk's share of one part is about kQueue / kParts = 2 per thread;
+        // the third slot keeps the usual overshoot in the same pass). The
+        // trip count is the same for every thread: the line count is a
+        // wave-wide operation.
+        for (int it = 0; it < n; it += kSlots * kSearchThreads) {
+            const int idx = it + (int)threadIdx.x;
+            int64_t i[kSlots], j[kSlots], gbase[kSlots], len[kSlots];
+            bool on[kSlots];
+            double x[kSlots];
 #pragma unroll
-            for (int k = 0; k < 2; ++k) {
+            for (int k = 0; k < kSlots; ++k) {
                 const int at = idx + k * kSearchThreads;
                 on[k] = at < n;
-                i[k] = on[k] ? sh_queue[at] : sh_queue[idx];
-            }
-            double x[2];
-#pragma unroll
-            for (int k = 0; k < 2; ++k) x[k] = multinomial_draw(seed, instance, i[k], W, capW);
-            int64_t gbase[2], len[2];
-#pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                gbase[k] = start + (int64_t)first_above_lds(sh_sub, groups, x[k]) * S;
+                i[k] = on[k] ? sh_queue[at] : 0;
+                x[k] = multinomial_draw(seed, instance, i[k], W, capW);
+                const int b = bk.of(x[k]);
+                const int glo = sh_guide[b], ghi = sh_guide[b + 1];
+                const int g = glo + first_above_lds(sh_sub + glo, ghi - glo + 1, x[k]);
+                gbase[k] = start + (int64_t)g * S;
                 len[k] = min(S, end - gbase[k]);
             }
 #pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                if (vec && len[k] == 16) {  // the whole line: count the C' <= x
-                    const double2 *g2 = reinterpret_cast<const double2 *>(C + gbase[k]);
-                    double2 c[8];
-#pragma unroll
-                    for (int h = 0; h < 8; ++h) c[h] = g2[h];
-                    int below_x = 0;
-#pragma unroll
-                    for (int h = 0; h < 8; ++h)
-                        below_x += (c[h].x <= x[k] ? 1 : 0) + (c[h].y <= x[k] ? 1 : 0);
-                    j[k] = gbase[k] + below_x;
-                } else {
-                    j[k] = gbase[k] + first_above(C + gbase[k], len[k], x[k]);
-                }
+            for (int k = 0; k < kSlots; ++k) {
+                if (__ballot(on[k]) == 0) continue;  // wave-uniform
+                const bool coop = on[k] && vec && len[k] == 16;
+                const int cnt = vec ? line_count_coop(C, x[k], gbase[k], coop) : 0;
+                if (on[k])
+                    j[k] = coop ? gbase[k] + cnt
+                                : gbase[k] + first_above(C + gbase[k], len[k], x[k]);
             }
 #pragma unroll
-            for (int k = 0; k < 2; ++k) {
+            for (int k = 0; k < kSlots; ++k) {
                 if (on[k]) {
                     anc[i[k]] = (int32_t)j[k];
                     if (rows.x_in) copy_row(rows, i[k], j[k], 0, 1);

@@ -134,6 +134,7 @@ struct WsView {
     int32_t *count;
     int32_t *win;
     double *sub;
+    uint16_t *guide;
     uint8_t *part;
 };
 
@@ -149,6 +150,7 @@ __device__ __forceinline__ WsView ws_view(char *ws, int64_t P)
     v.count = reinterpret_cast<int32_t *>(ws + L.count);
     v.win = reinterpret_cast<int32_t *>(ws + L.win);
     v.sub = reinterpret_cast<double *>(ws + L.sub);
+    v.guide = reinterpret_cast<uint16_t *>(ws + L.guide);
     v.part = reinterpret_cast<uint8_t *>(ws + L.part);
     return v;
 }
