@@ -267,6 +267,38 @@ def test_prefix_heavy_particle_overflow_chunks(rs, kind):
     assert int(host(off)[123457]) > P // 2
 
 
+def test_multinomial_heavy_particle_guide(rs):
+    # one particle carries almost all weight: its group covers almost every
+    # bucket of its part's guide table, and the other parts hold next to none
+    P = 300000
+    lw = np.full(P, -40.0, dtype=np.float32)
+    lw[123457] = 0.0
+    lw[5] = -3.0
+    lw[299990] = -2.0
+    anc_o, _, C_o = ORACLE_FN["multinomial"](lw, 2, 1, want_cumw=True)
+    C = torch.empty(P, dtype=torch.float64, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    anc_g = host(rs.resample_multinomial(dev(lw), 2, 1, cumw=C, status=st))
+    assert int(host(st)[0]) == 0
+    check_cumw(host(C), C_o)
+    explained_mismatches("multinomial", anc_g, anc_o, C_o, 2, 1)
+    assert np.count_nonzero(anc_g == 123457) > P // 2
+
+
+@pytest.mark.parametrize("P", [(1 << 20) + 1, 3_000_001])
+def test_multinomial_beyond_one_line_groups(rs, P):
+    # above 2^20 particles a group holds more than 16 C' (one 128-byte line),
+    # so the group is searched per lane instead of by eight lanes together
+    seed, inst = 8, 5
+    lw = workloads.normal_logweights(P, 2.0, seed)
+    say("multinomial P =", P)
+    anc_o, _, C_o = ORACLE_FN["multinomial"](lw, seed, inst, want_cumw=True)
+    C = torch.empty(P, dtype=torch.float64, device="cuda")
+    anc_g = host(rs.resample_multinomial(dev(lw), seed, inst, cumw=C))
+    check_cumw(host(C), C_o)
+    explained_mismatches("multinomial", anc_g, anc_o, C_o, seed, inst)
+
+
 @pytest.mark.parametrize("kind", PREFIX)
 def test_prefix_edge_weights(rs, kind):
     fn = getattr(rs, f"resample_{kind}")
