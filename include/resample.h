@@ -76,7 +76,8 @@ const char *rs_last_hip_error(void);
 /*
  * Bytes of workspace the prefix-sum resamplers need for P particles: tile
  * partial sums, tile boundaries, per-tile draw counts, the fill table and,
- * for the multinomial resampler, the cumulative weights (pooled temporaries;
+ * for the multinomial resampler, the cumulative weights with the search's
+ * group ends, guide table and one part byte per draw (pooled temporaries;
  * Sec. 3 replaces per-call allocations with reused pooled arrays). 0 for
  * RS_METROPOLIS. The workspace needs no initialisation: every call writes
  * what it reads, so one buffer serves any sequence of ordered calls.
