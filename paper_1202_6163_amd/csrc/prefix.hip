@@ -192,9 +192,10 @@ __device__ __forceinline__ void fill_guide(uint16_t *guide, int from, int to, ui
 }
 
 // ------------------------------------------------------ multinomial
-// Launch 3m: one block per tile writes C' for the tile, and into ws.sub the
-// last C' of every sub_stride(P)-particle group of each part (the last group
-// of a part ends at the part's end).
+// Launch 3m: one block per tile writes C' for the tile; into ws.sub the last
+// C' of every sub_stride(P)-particle group of each part (the last group of a
+// part ends at the part's end) and the guide entries those groups own; and
+// the part byte of each of the tile's draws.
 __global__ __launch_bounds__(kTileThreads) void cumulative_kernel(const float *__restrict__ lw,
                                                                   int64_t P, double *C,
                                                                   char *ws_raw, uint64_t seed,
