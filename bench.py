@@ -21,6 +21,7 @@ Beside it the JSON line carries:
 """
 import argparse
 import hashlib
+import re
 import json
 import os
 import platform
@@ -337,9 +338,17 @@ KERNEL_SOURCES = {
 }
 
 
+def _code_only(text):
+    """C++ source without its comments and blank lines (a comment edit does
+    not change the kernel the counters measured)."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+
+
 def source_hash(kernel):
-    """Hash of the kernel family's sources, plus the stored launch tuning for
-    Metropolis (it selects the kernel variant that runs)."""
+    """Hash of the kernel family's code (comments stripped), plus the stored
+    launch tuning for Metropolis (it selects the kernel variant that runs)."""
     h = hashlib.sha256()
     pkg = os.path.join(ROOT, "paper_1202_6163_amd")
     files = [os.path.join("csrc", name) for name in sorted(KERNEL_SOURCES[kernel])]
@@ -347,8 +356,11 @@ def source_hash(kernel):
         files.append("tuning.json")
     for name in files:
         try:
-            with open(os.path.join(pkg, name), "rb") as f:
-                h.update(name.encode() + f.read())
+            with open(os.path.join(pkg, name), "r", encoding="utf-8") as f:
+                text = f.read()
+            if name.endswith((".hip", ".h", ".cpp")):
+                text = _code_only(text)
+            h.update(name.encode() + text.encode())
         except OSError:
             h.update(name.encode() + b"<missing>")
     return h.hexdigest()
