@@ -397,11 +397,13 @@ def test_offspring_bad_ancestor(rs):
     assert np.array_equal(off, [1, 1, 2, 0, 0, 1])  # -1 skipped, 5 counted
 
 
-@pytest.mark.parametrize("P", [1, 5, 1023, 4096, 100003, 1 << 20])
-@pytest.mark.parametrize("D", [1, 3, 4, 8, 16])
+# every D up to 100003 particles; at the full size the D of the sweep (4) and D = 1
+COPY_CASES = [(P, D) for P in (1, 5, 1023, 4096, 100003) for D in (1, 3, 4, 8, 16)]
+COPY_CASES += [(1 << 20, 1), (1 << 20, 4)]
+
+
+@pytest.mark.parametrize("P,D", COPY_CASES)
 def test_permute_copy_bit_exact(rs, P, D):
-    if P == 1 << 20 and D not in (1, 4):
-        pytest.skip("full size covered for the D of the sweep")
     rng = np.random.default_rng(D)
     x = workloads.state_rows_exact(P, D)
     x[rng.integers(0, P, min(P, 10))] = np.nan  # bits, not values
