@@ -655,26 +655,48 @@ def cpu_baseline(args, workloads):
     P, D, B = args.P, args.D, args.B
     lw = workloads.normal_logweights(P, args.sigma, 0)
     x = workloads.state_rows_normal(P, D, 0)
+    # one core, pinned for the measurement (the oracle is single-threaded C)
+    allowed = sorted(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else []
+    pinned = None
+    if allowed:
+        pinned = allowed[0]
+        os.sched_setaffinity(0, {pinned})
     times = []
-    t_start = time.perf_counter()
-    while True:
-        t0 = time.perf_counter()
-        for kind in ("metropolis", "stratified", "systematic", "multinomial"):
-            if kind == "metropolis":
-                anc, _ = oracle.metropolis(lw, B, 1, 0)
-            else:
-                anc, _ = getattr(oracle, kind)(lw, 1, 0)
-            oracle.ancestors_to_offspring(anc)
-            oracle.permute_copy(anc, x)
-        times.append(time.perf_counter() - t0)
-        if time.perf_counter() - t_start > args.cpu_seconds or len(times) >= 20:
-            break
+    try:
+        t_start = time.perf_counter()
+        while True:
+            t0 = time.perf_counter()
+            for kind in ("metropolis", "stratified", "systematic", "multinomial"):
+                if kind == "metropolis":
+                    anc, _ = oracle.metropolis(lw, B, 1, 0)
+                else:
+                    anc, _ = getattr(oracle, kind)(lw, 1, 0)
+                oracle.ancestors_to_offspring(anc)
+                oracle.permute_copy(anc, x)
+            times.append(time.perf_counter() - t0)
+            if time.perf_counter() - t_start > args.cpu_seconds or len(times) >= 20:
+                break
+    finally:
+        if allowed:
+            os.sched_setaffinity(0, set(allowed))
     t = float(np.mean(times))
     return {"value": 4 * P / t, "unit": "particles/s", "cores": 1, "kind": "oracle",
-            "sample": f"{len(times)} full steps at P=2^20 (4 resamplers + offspring + copy, "
+            "sample": f"{len(times)} full steps at P={P} (4 resamplers + offspring + copy, "
                       f"Metropolis B={B}), single-threaded C oracle",
-            "seconds_per_step": t, "host_cpu": platform.processor() or platform.machine(),
-            "host_nproc": os.cpu_count()}
+            "seconds_per_step": t, "host_cpu": cpu_model(), "pinned_cpu": pinned,
+            "allowed_cpus": len(allowed), "host_nproc": os.cpu_count()}
+
+
+def cpu_model():
+    """The host CPU's model name (Linux), else the platform's description."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
 
 
 if __name__ == "__main__":
