@@ -28,7 +28,9 @@
 // unsorted, so that resampler stores C (launch 3m) and searches it per draw
 // (launch 4m): the particles are split in eight parts, one per XCD, each
 // searched by the blocks that XCD runs (every 16th C' of the part staged in
-// LDS, then one 128-byte line of C).
+// LDS, then one 128-byte line of C). Up to 64 tiles the cumulative blocks
+// rebuild the boundaries themselves (no table launch); up to two tiles one
+// block does the whole multinomial resampling in one launch.
 //
 // Rounding: inside a tile C'_j = min(B_{t-1} + L_j, B_t), where L_j is a
 // zero-weight-aware running maximum of the tile's scan, and C'_j = B_t from
@@ -196,26 +198,62 @@ __device__ __forceinline__ void fill_guide(uint16_t *guide, int from, int to, ui
 // C' of every sub_stride(P)-particle group of each part (the last group of a
 // part ends at the part's end) and the guide entries those groups own; and
 // the part byte of each of the tile's draws.
+// With FUSED (at most kFusedTableTiles tiles) there is no table launch: every
+// block rebuilds the tile boundaries in LDS from the tile sums (the same
+// function and order as the table launch, so the same bits), writes its own
+// tile's boundary for the search, and block 0 writes the header.
+template <bool FUSED>
 __global__ __launch_bounds__(kTileThreads) void cumulative_kernel(const float *__restrict__ lw,
                                                                   int64_t P, double *C,
                                                                   char *ws_raw, uint64_t seed,
-                                                                  uint32_t instance)
+                                                                  uint32_t instance,
+                                                                  int32_t *status)
 {
     __shared__ double Cs[kTile];
+    __shared__ double sh_bound[FUSED ? kFusedTableTiles : 1];
     const WsView ws = ws_view(ws_raw, P);
     const int64_t t = blockIdx.x;
     float v[4];
     load_tile4(lw, P, t, v);
-    if (ws.h->flags) {
+    int flags;
+    float m;
+    double W;
+    const double *bound = ws.bound;
+    if (FUSED) {
+        const TableSums sums = boundaries(ws, P, sh_bound);
+        flags = sums.flags;
+        m = sums.m;
+        W = sums.W;
+        bound = sh_bound;
+        if (threadIdx.x == 0) {
+            if (!flags) ws.bound[t] = sh_bound[t];
+            if (t == 0) {
+                WsHeader *h = ws.h;
+                h->flags = flags;
+                h->m = m;
+                h->W = W;
+                h->delta = W / (double)P;
+                h->lse = flags ? ((flags & (kFlagNan | kFlagPosInf)) ? (double)NAN
+                                                                     : -(double)INFINITY)
+                               : (double)m + log(W);
+                if (flags) raise_flags(status, flags);
+            }
+        }
+    } else {
+        flags = ws.h->flags;
+        m = ws.h->m;
+        W = ws.h->W;
+    }
+    if (flags) {
         const int64_t base = t * kTile + 4 * (int64_t)threadIdx.x;
         for (int k = 0; k < 4; ++k)
             if (base + k < P) C[base + k] = (double)NAN;
         return;
     }
-    const double Blo = t > 0 ? ws.bound[t - 1] : 0.0;
+    const double Blo = t > 0 ? bound[t - 1] : 0.0;
     double w[4], Cv[4];
-    tile_weights(v, ws.h->m, w);
-    tile_cumulative(w, Blo, ws.bound[t], Cs, Cv);
+    tile_weights(v, m, w);
+    tile_cumulative(w, Blo, bound[t], Cs, Cv);
     store_cumw(C, P, t, Cv);
     const int64_t Pp = part_size(P), S = sub_stride(P), ns = sub_per_part(P);
     // the group ends of this tile, and their guide entries: group g writes
@@ -226,7 +264,7 @@ __global__ __launch_bounds__(kTileThreads) void cumulative_kernel(const float *_
     // earlier tile's last C', which equals that tile's bound bit for bit.
     const int xt = (int)(t * kTile / Pp);  // a part is whole tiles
     double plo, phi;
-    part_range(ws.bound, P, xt, &plo, &phi);
+    part_range(bound, P, xt, &plo, &phi);
     const Buckets bk = make_buckets(plo, phi, (int)((min((xt + 1) * Pp, P) - xt * Pp + S - 1) / S));
     uint16_t *guide = ws.guide + xt * guide_stride(P);
 #pragma unroll
@@ -241,7 +279,7 @@ __global__ __launch_bounds__(kTileThreads) void cumulative_kernel(const float *_
             int bp = -1;
             if (g > 0) {
                 const int64_t pe = xt * Pp + g * S - 1;
-                bp = bk.of(pe >= t * kTile ? Cs[pe - t * kTile] : ws.bound[pe / kTile]);
+                bp = bk.of(pe >= t * kTile ? Cs[pe - t * kTile] : bound[pe / kTile]);
             }
             if (bg > bp) fill_guide(guide, bp + 1, bg + 1, (uint16_t)g);
             if (e == end - 1) fill_guide(guide, max(bg, bp) + 1, bk.nb + 1, (uint16_t)g);
@@ -250,12 +288,12 @@ __global__ __launch_bounds__(kTileThreads) void cumulative_kernel(const float *_
     // The part of each of the tile's draws [t kTile, (t+1) kTile) (two Philox
     // blocks per thread): part y holds C' in [B_{y Pp / kTile - 1}, the next
     // part's bound), so the search reads one byte per draw instead of redrawing.
-    const double W = ws.h->W, capW = below(W);
+    const double capW = below(W);
     const int parts = (int)((P + Pp - 1) / Pp);
     double lo[kParts];
 #pragma unroll
     for (int y = 1; y < kParts; ++y)
-        lo[y] = y < parts ? ws.bound[y * Pp / kTile - 1] : (double)INFINITY;
+        lo[y] = y < parts ? bound[y * Pp / kTile - 1] : (double)INFINITY;
     uint32_t ids = 0;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -507,6 +545,84 @@ __global__ __launch_bounds__(kSearchThreads) void multinomial_search_kernel(
     }
 }
 
+// Multinomial for at most kSmallMultiTiles tiles in one block and one launch:
+// the tile sums, the boundaries and each tile's C' come from the same
+// functions, in the same order, as in the tile, table and cumulative launches
+// (so the same bits), kept in LDS; then each thread bisects C' for eight
+// draws at a time. At these sizes the four dependent launches of the general
+// path cost more than the whole resampling.
+constexpr int64_t kSmallMultiTiles = 2;  // one block runs the tiles one after another
+constexpr int kSmallDraws = 8;           // draws per thread per pass
+
+__global__ __launch_bounds__(kTileThreads) void multinomial_small_kernel(
+    const float *__restrict__ lw, int32_t *__restrict__ anc, int64_t P, uint64_t seed,
+    uint32_t instance, double *C, char *ws_raw, int32_t *status, Rows rows)
+{
+    __shared__ double sh_C[kSmallMultiTiles * kTile];
+    __shared__ double sh_bound[kSmallMultiTiles];
+    const WsView ws = ws_view(ws_raw, P);
+    const int64_t n = num_tiles(P);
+    for (int64_t t = 0; t < n; ++t) tile_reduce_body(lw, P, t, ws_raw);
+    __threadfence_block();
+    __syncthreads();
+    const TableSums sums = boundaries(ws, P, sh_bound);
+    if (threadIdx.x == 0) {
+        WsHeader *h = ws.h;
+        h->flags = sums.flags;
+        h->m = sums.m;
+        h->W = sums.W;
+        h->delta = sums.W / (double)P;
+        h->lse = sums.flags ? ((sums.flags & (kFlagNan | kFlagPosInf)) ? (double)NAN
+                                                                       : -(double)INFINITY)
+                            : (double)sums.m + log(sums.W);
+        if (sums.flags) raise_flags(status, sums.flags);
+    }
+    if (sums.flags) {  // flagged input: identity ancestors and rows
+        for (int64_t i = threadIdx.x; i < P; i += kTileThreads) {
+            anc[i] = (int32_t)i;
+            C[i] = (double)NAN;
+            if (rows.x_in) copy_row(rows, i, i, 0, 1);
+        }
+        return;
+    }
+    for (int64_t t = 0; t < n; ++t) {
+        float v[4];
+        load_tile4(lw, P, t, v);
+        double w[4], Cv[4];
+        tile_weights(v, sums.m, w);
+        tile_cumulative(w, t > 0 ? sh_bound[t - 1] : 0.0, sh_bound[t], sh_C + t * kTile, Cv);
+        store_cumw(C, P, t, Cv);
+    }
+    // a_i = first j with C'_j > x_i; C'_{P-1} = W exceeds every draw
+    const double W = sums.W, capW = below(W);
+    const int np = (int)P;
+    for (int i0 = 0; i0 < np; i0 += kSmallDraws * kTileThreads) {
+        double x[kSmallDraws];
+        int j[kSmallDraws];
+#pragma unroll
+        for (int k = 0; k < kSmallDraws; ++k) {
+            const int i = i0 + k * kTileThreads + (int)threadIdx.x;
+            x[k] = multinomial_draw(seed, instance, i < np ? i : 0, W, capW);
+            j[k] = 0;
+        }
+        for (int len = np; len > 1;) {  // the bisection of first_above_lds, eight at a time
+            const int half = len >> 1;
+#pragma unroll
+            for (int k = 0; k < kSmallDraws; ++k)
+                j[k] = sh_C[j[k] + half - 1] <= x[k] ? j[k] + half : j[k];
+            len -= half;
+        }
+#pragma unroll
+        for (int k = 0; k < kSmallDraws; ++k) {
+            const int i = i0 + k * kTileThreads + (int)threadIdx.x;
+            if (i < np) {
+                anc[i] = j[k];
+                if (rows.x_in) copy_row(rows, i, j[k], 0, 1);
+            }
+        }
+    }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
@@ -517,6 +633,12 @@ int launch_prefix(int kind, const float *lw, int32_t *anc, int32_t *off, int64_t
     const int64_t n = num_tiles(P);
     char *w = static_cast<char *>(ws);
     const dim3 tb(kTileThreads);
+    if (kind == kMultinomial && n <= kSmallMultiTiles) {
+        double *C = cumw ? cumw : reinterpret_cast<double *>(w + ws_layout(P, true).cumw);
+        hipLaunchKernelGGL(multinomial_small_kernel, dim3(1), tb, 0, stream, lw, anc, P, seed,
+                           instance, C, w, status, rows);
+        return launch_status();
+    }
     hipLaunchKernelGGL(tile_reduce_kernel, dim3((uint32_t)n), tb, 0, stream, lw, P, w);
     switch (kind) {
     case kStratified:
@@ -531,10 +653,16 @@ int launch_prefix(int kind, const float *lw, int32_t *anc, int32_t *off, int64_t
         break;
     case kMultinomial: {
         double *C = cumw ? cumw : reinterpret_cast<double *>(w + ws_layout(P, true).cumw);
-        if (const int rc = launch_table<kMultinomial>(P, seed, instance, w, status, nullptr, stream))
-            return rc;
-        hipLaunchKernelGGL(cumulative_kernel, dim3((uint32_t)n), tb, 0, stream, lw, P, C, w, seed,
-                           instance);
+        if (n <= kFusedTableTiles) {
+            hipLaunchKernelGGL(cumulative_kernel<true>, dim3((uint32_t)n), tb, 0, stream, lw, P, C,
+                               w, seed, instance, status);
+        } else {
+            if (const int rc = launch_table<kMultinomial>(P, seed, instance, w, status, nullptr,
+                                                          stream))
+                return rc;
+            hipLaunchKernelGGL(cumulative_kernel<false>, dim3((uint32_t)n), tb, 0, stream, lw, P,
+                               C, w, seed, instance, status);
+        }
         const size_t smem = (size_t)sub_per_part(P) * sizeof(double);
         if (allow_dynamic_lds(reinterpret_cast<const void *>(&multinomial_search_kernel), smem))
             return -3;
