@@ -847,10 +847,26 @@ __device__ void fill_body(const float *__restrict__ lw, int32_t *__restrict__ an
         double x[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) x[k] = fmin(((double)(o0 + k) + U[k]) * delta, cap);
+        // the draws are non-decreasing, so a_0 <= a_k <= a_7: bisect the whole
+        // tile for the first and last draw only, and the six between within
+        // [a_0, a_7] (usually a few particles), all six in lockstep; the same
+        // first-above rule, so the same ancestors as eight full bisections
         int32_t a[8];
         const int32_t tile_base = (int32_t)(t * kTile);
+        const int j0 = search_tile(Cs, x[0]), j7 = search_tile(Cs, x[7]);
+        int jm[6];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) a[k] = tile_base + search_tile(Cs, x[k]);
+        for (int k = 0; k < 6; ++k) jm[k] = j0;
+        for (int len = j7 - j0 + 1; len > 1;) {
+            const int half = len >> 1;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) jm[k] = Cs[jm[k] + half - 1] <= x[k + 1] ? jm[k] + half : jm[k];
+            len -= half;
+        }
+        a[0] = tile_base + j0;
+        a[7] = tile_base + j7;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) a[k + 1] = tile_base + jm[k];
         if (anc) {
             const bool full = (o0 >= ob) && (o0 + 8 <= oe) && ((((uintptr_t)(anc + o0)) & 15) == 0);
             if (full) {
