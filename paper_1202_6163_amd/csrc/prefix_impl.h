@@ -605,9 +605,9 @@ __device__ __forceinline__ int64_t first_bound_above(const double *bound, int64_
 // exact counts of the ancestors the fill writes. Called by the whole block.
 template <int KIND>
 __device__ void tile_offspring(int32_t *off, int64_t P, int64_t t, int64_t lo, int64_t hi,
-                               int64_t oe, int64_t a0, const int32_t *sh_anc, const double *Cs,
-                               double W, double delta, uint64_t seed, uint32_t instance,
-                               double u_sys)
+                               int64_t oe, int64_t a0, const int32_t a[8],
+                               const int32_t *sh_anc, const double *Cs, double W, double delta,
+                               uint64_t seed, uint32_t instance, double u_sys)
 {
     __shared__ int16_t sh_start[kTile], sh_stop[kTile];
     const int64_t base = t * kTile;
@@ -621,14 +621,21 @@ __device__ void tile_offspring(int32_t *off, int64_t P, int64_t t, int64_t lo, i
             sh_stop[4 * threadIdx.x + k] = 0;
         }
         __syncthreads();
+        // the thread's own slots are in registers; only the neighbours across
+        // thread boundaries come from LDS
+        const int rb = 8 * (int)threadIdx.x;
+        const int32_t before = (rb > r0 && rb < r1) ? sh_anc[rb - 1] : -1;
+        const int32_t after = (rb + 7 >= r0 && rb + 7 < r1 - 1) ? sh_anc[rb + 8] : -1;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            const int r = 8 * (int)threadIdx.x + k;
+            const int r = rb + k;
             if (r >= r0 && r < r1) {
-                const int32_t a = sh_anc[r];
-                const int q = (int)(a - base);
-                if (r == r0 || sh_anc[r - 1] != a) sh_start[q] = (int16_t)r;
-                if (r == r1 - 1 || sh_anc[r + 1] != a) sh_stop[q] = (int16_t)(r + 1);
+                const int32_t ak = a[k];
+                const int32_t prev = k == 0 ? before : a[k - 1];
+                const int32_t next = k == 7 ? after : a[k + 1];
+                const int q = (int)(ak - base);
+                if (r == r0 || prev != ak) sh_start[q] = (int16_t)r;
+                if (r == r1 - 1 || next != ak) sh_stop[q] = (int16_t)(r + 1);
             }
         }
         __syncthreads();
@@ -832,6 +839,7 @@ __device__ void fill_body(const float *__restrict__ lw, int32_t *__restrict__ an
 
     const bool keep = x_in || want_off;  // ancestors needed again from LDS
     const int64_t o0 = a0 + 8 * (int64_t)threadIdx.x;
+    int32_t a[8];  // this thread's slots' ancestors (defined for the slots in [ob, oe))
     if (o0 + 8 > ob && o0 < oe) {
         double U[8];
         if (KIND == kStratified) {
@@ -851,7 +859,6 @@ __device__ void fill_body(const float *__restrict__ lw, int32_t *__restrict__ an
         // tile for the first and last draw only, and the six between within
         // [a_0, a_7] (usually a few particles), all six in lockstep; the same
         // first-above rule, so the same ancestors as eight full bisections
-        int32_t a[8];
         const int32_t tile_base = (int32_t)(t * kTile);
         const int j0 = search_tile(Cs, x[0]), j7 = search_tile(Cs, x[7]);
         int jm[6];
@@ -886,8 +893,8 @@ __device__ void fill_body(const float *__restrict__ lw, int32_t *__restrict__ an
     }
     if (keep) __syncthreads();
     if (want_off)
-        tile_offspring<KIND>(off, P, t, sh_range[4], sh_range[5], oe, a0, sh_anc, Cs, W, delta,
-                             seed, instance, u_sys);
+        tile_offspring<KIND>(off, P, t, sh_range[4], sh_range[5], oe, a0, a, sh_anc, Cs, W,
+                             delta, seed, instance, u_sys);
     if (x_in) {
         int fl = 0;
         copy_rows_from_lds(sh_anc, a0, ob, oe, x_in, x_out, D, P, &fl);
