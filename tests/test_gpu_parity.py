@@ -173,7 +173,7 @@ def offspring_of(anc):
 def check_offspring(off_g, anc_g):
     """The resampler's own offspring counts are exactly the counts of its ancestors."""
     assert np.array_equal(np.asarray(off_g), offspring_of(anc_g))
-SIZES = [1, 2, 3, 9, 1023, 1024, 1025, 4097, 100003, 1 << 16]
+SIZES = [1, 2, 3, 9, 1023, 1024, 1025, 2048, 2049, 4097, 100003, 1 << 16]
 
 
 @pytest.mark.parametrize("kind", PREFIX)
@@ -332,27 +332,36 @@ def test_prefix_edge_weights(rs, kind):
     assert np.all(host(fn(dev(one), 1, 0)) == 2999)
 
 
+# sizes for the three launch structures: one block (multinomial up to two
+# tiles), fused table (up to 64 tiles), separate table launch
+FLAG_SIZES = [1000, 2500, 100003]
+
+
 @pytest.mark.parametrize("kind", PREFIX)
-def test_prefix_flags(rs, kind):
+@pytest.mark.parametrize("P", FLAG_SIZES)
+def test_prefix_flags(rs, kind, P):
     fn = getattr(rs, f"resample_{kind}")
     for bad, flag in ((np.nan, rs.FLAG_NAN), (np.inf, rs.FLAG_POSINF)):
-        lw = np.zeros(2500, dtype=np.float32)
-        lw[1700] = bad
+        lw = np.zeros(P, dtype=np.float32)
+        lw[2 * P // 3] = bad
         st = torch.zeros(1, dtype=torch.int32, device="cuda")
         kw = {}
         if kind in SORTED:
-            kw["off"] = torch.full((2500,), -1, dtype=torch.int32, device="cuda")
-        anc = host(fn(dev(lw), 1, 0, status=st, **kw))
+            kw["off"] = torch.full((P,), -1, dtype=torch.int32, device="cuda")
+        C = torch.zeros(P, dtype=torch.float64, device="cuda")
+        anc = host(fn(dev(lw), 1, 0, status=st, cumw=C, **kw))
         assert int(host(st)[0]) == flag
-        assert np.array_equal(anc, np.arange(2500))
+        assert np.array_equal(anc, np.arange(P))
+        assert np.all(np.isnan(host(C)))
         if kw:
             assert np.all(host(kw["off"]) == 1)
-    lw = np.full(2500, -np.inf, dtype=np.float32)
+    lw = np.full(P, -np.inf, dtype=np.float32)
     st = torch.zeros(1, dtype=torch.int32, device="cuda")
     anc = host(fn(dev(lw), 1, 0, status=st))
     assert int(host(st)[0]) == rs.FLAG_ALL_NEGINF
+    assert np.array_equal(anc, np.arange(P))
     # the workspace is clean again: a good call right after succeeds
-    lw = workloads.normal_logweights(2500, 1.0, 1)
+    lw = workloads.normal_logweights(P, 1.0, 1)
     st.zero_()
     anc = host(fn(dev(lw), 1, 0, status=st))
     assert int(host(st)[0]) == 0
