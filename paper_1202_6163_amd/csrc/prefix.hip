@@ -333,14 +333,15 @@ __device__ __forceinline__ int64_t first_above(const double *a, int64_t len, dou
 // inverse-CDF sampling): the part's C' range is cut into as many equal buckets
 // as there are groups, and guide[b] is the first group whose end falls in
 // bucket b or later. It then scans the part bytes of its share of the draws in
-// chunks (16 per thread), queues the draws of its part in LDS (wave-aggregated
+// chunks (32 per thread), queues the draws of its part in LDS (wave-aggregated
 // slots), and every thread takes queued draws, redraws x, bisects only the
 // groups [guide[b], guide[b + 1]] of x's bucket (about one on average) and
 // counts the group's 16 C' (one 128-byte line, up to 2^20 particles), eight
 // lanes reading each line together.
 constexpr int kSearchThreads = 1024;
-constexpr int kIdsPerThread = 16;
-constexpr int kQueue = kSearchThreads * kIdsPerThread;
+constexpr int kIdsPerThread = 32;
+constexpr int kQueue = kSearchThreads * kIdsPerThread;  // draws per chunk
+static_assert(kQueue <= 65536, "queue entries are 16-bit offsets into the chunk");
 constexpr int kSlots = 3;
 
 __device__ __forceinline__ double multinomial_draw(uint64_t seed, uint32_t instance, int64_t i,
@@ -406,7 +407,7 @@ __global__ __launch_bounds__(kSearchThreads) void multinomial_search_kernel(
     uint32_t instance, char *ws_raw, Rows rows)
 {
     extern __shared__ double sh_sub[];
-    __shared__ int32_t sh_queue[kQueue];
+    __shared__ uint16_t sh_queue[kQueue];  // draw index - chunk start
     __shared__ __align__(16) uint16_t sh_guide[kSubMax + 8];
     static_assert(kSubMax % 8 == 0, "guide rows are whole 16-byte vectors");
     __shared__ int32_t sh_count[2];
@@ -426,7 +427,8 @@ __global__ __launch_bounds__(kSearchThreads) void multinomial_search_kernel(
     const int groups = start < P ? (int)((end - start + S - 1) / S) : 0;
     double plo = 0.0, phi = 0.0;
     if (start < P) part_range(ws.bound, P, part, &plo, &phi);
-    uint4 pv = load_part_bytes(ws.part, d0 + (int64_t)kIdsPerThread * threadIdx.x, d1);
+    uint4 pv0 = load_part_bytes(ws.part, d0 + (int64_t)kIdsPerThread * threadIdx.x, d1);
+    uint4 pv1 = load_part_bytes(ws.part, d0 + (int64_t)kIdsPerThread * threadIdx.x + 16, d1);
     constexpr int kStage = (int)(kSubMax / kSearchThreads);
     static_assert(kSubMax % kSearchThreads == 0, "whole staging rounds");
     double stage[kStage];
@@ -470,17 +472,19 @@ __global__ __launch_bounds__(kSearchThreads) void multinomial_search_kernel(
     const int lane = lane_id();
     int parity = 0;
     for (int64_t c0 = d0; c0 < d1; c0 += kQueue) {
-        // (1) this thread's 16 part bytes; bit b of keep marks draw i0 + b as ours
+        // (1) this thread's 32 part bytes; bit b of keep marks draw i0 + b as ours
         const int64_t i0 = c0 + (int64_t)kIdsPerThread * threadIdx.x;
         uint32_t keep = 0;
         {
-            const uint32_t w4[4] = {pv.x, pv.y, pv.z, pv.w};
+            const uint32_t w8[8] = {pv0.x, pv0.y, pv0.z, pv0.w, pv1.x, pv1.y, pv1.z, pv1.w};
 #pragma unroll
             for (int b = 0; b < kIdsPerThread; ++b)
-                if (i0 + b < d1 && ((w4[b >> 2] >> (8 * (b & 3))) & 0xffu) == (uint32_t)part)
+                if (i0 + b < d1 && ((w8[b >> 2] >> (8 * (b & 3))) & 0xffu) == (uint32_t)part)
                     keep |= 1u << b;
         }
-        pv = load_part_bytes(ws.part, i0 + kQueue, d1);  // the next chunk's, while this one runs
+        // the next chunk's, while this one runs
+        pv0 = load_part_bytes(ws.part, i0 + kQueue, d1);
+        pv1 = load_part_bytes(ws.part, i0 + kQueue + 16, d1);
         // (2) queue slots: a wave-wide prefix of the counts, one LDS atomic per wave
         const int cnt = __popc(keep);
         int incl = cnt;
@@ -496,7 +500,7 @@ __global__ __launch_bounds__(kSearchThreads) void multinomial_search_kernel(
         while (keep) {
             const int bit = __ffs((int)keep) - 1;
             keep &= keep - 1;
-            sh_queue[pos++] = (int32_t)(i0 + bit);
+            sh_queue[pos++] = (uint16_t)(i0 + bit - c0);
         }
         __syncthreads();
         const int n = sh_count[parity];
@@ -515,7 +519,7 @@ __global__ __launch_bounds__(kSearchThreads) void multinomial_search_kernel(
             for (int k = 0; k < kSlots; ++k) {
                 const int at = idx + k * kSearchThreads;
                 on[k] = at < n;
-                i[k] = on[k] ? sh_queue[at] : 0;
+                i[k] = on[k] ? c0 + sh_queue[at] : 0;
                 x[k] = multinomial_draw(seed, instance, i[k], W, capW);
                 const int b = bk.of(x[k]);
                 const int glo = sh_guide[b], ghi = sh_guide[b + 1];
@@ -666,8 +670,9 @@ int launch_prefix(int kind, const float *lw, int32_t *anc, int32_t *off, int64_t
         const size_t smem = (size_t)sub_per_part(P) * sizeof(double);
         if (allow_dynamic_lds(reinterpret_cast<const void *>(&multinomial_search_kernel), smem))
             return -3;
-        // K blocks per part: one per CU of an XCD at most, a chunk each at least
-        int64_t K = (P + kQueue - 1) / kQueue;
+        // K blocks per part: one per CU of an XCD at most, and 16384 draws
+        // each at least (a block's range is then one chunk up to 2^20)
+        int64_t K = (P + 16383) / 16384;
         K = K < 1 ? 1 : (K > 32 ? 32 : K);
         const int64_t grid = kParts * K;
         hipLaunchKernelGGL(multinomial_search_kernel, dim3((uint32_t)grid), dim3(kSearchThreads),
