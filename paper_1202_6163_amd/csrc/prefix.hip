@@ -328,11 +328,11 @@ __device__ __forceinline__ int64_t first_above(const double *a, int64_t len, dou
 // Launch 4m: kParts x K blocks of 1024 threads; blocks b = x, x + kParts, ...
 // serve part x (the draws whose ancestor lies in it), so with the round-robin
 // placement of blocks on the XCDs one XCD searches one part and its slice of
-// C stays in that XCD's L2. A block stages the part's group ends (every S-th
-// C') in LDS and builds a guide table over them (Chen and Asau's method for
-// inverse-CDF sampling): the part's C' range is cut into as many equal buckets
-// as there are groups, and guide[b] is the first group whose end falls in
-// bucket b or later. It then scans the part bytes of its share of the draws in
+// C stays in that XCD's L2. A block stages in LDS the part's group ends
+// (every S-th C') and the guide table the cumulative launch built over them
+// (Chen and Asau's method for inverse-CDF sampling: the part's C' range is cut
+// into as many equal buckets as there are groups, and guide[b] is the first
+// group whose end falls in bucket b or later). It then scans the part bytes of its share of the draws in
 // chunks (32 per thread), queues the draws of its part in LDS (wave-aggregated
 // slots), and every thread takes queued draws, redraws x, bisects only the
 // groups [guide[b], guide[b + 1]] of x's bucket (about one on average) and
