@@ -131,16 +131,22 @@ class GpuExecutor:
     """Runs batches on n_streams HIP streams with the library's batched launch;
     completion times come from HIP events on the device clock."""
 
-    def __init__(self, n_streams=4, tuning=None, keep_results=False):
+    def __init__(self, n_streams=4, tuning=None, keep_results=False, max_single_p=1 << 20):
         import torch
 
-        from . import workloads
-        self.torch, self.workloads = torch, workloads
+        from . import api, workloads
+        self.torch, self.workloads, self.api = torch, workloads, api
         self.dev = torch.device("cuda", torch.cuda.current_device())
         self.streams = [torch.cuda.Stream(self.dev) for _ in range(n_streams)]
         self.n_streams = n_streams
         self.tuning = tuning
         self.keep_results = keep_results
+        # A batch of one request goes through the single-call entry points
+        # (the same results as the batched launch, without building a plan);
+        # each stream keeps a prefix workspace for up to max_single_p particles.
+        self.max_single_p = int(max_single_p)
+        self.single_ws = [api.workspace(self.max_single_p, api.STRATIFIED, self.dev, stream=st)
+                          for st in self.streams]
         self.t0_event = torch.cuda.Event(enable_timing=True)
         self.t0_event.record()
         torch.cuda.synchronize()
@@ -169,6 +175,8 @@ class GpuExecutor:
         from .batch import Batch
         torch = self.torch
         stream = self.streams[s]
+        if len(reqs) == 1 and reqs[0].P <= self.max_single_p:
+            return self._submit_single(s, reqs[0])
         insts = []
         for r in reqs:
             st = r.state
@@ -184,6 +192,26 @@ class GpuExecutor:
             ev = torch.cuda.Event(enable_timing=True)
             ev.record(stream)
         return (b, ev)
+
+    def _submit_single(self, s, r):
+        torch, api = self.torch, self.api
+        stream = self.streams[s]
+        st = r.state
+        stream.wait_event(st["ready"])
+        inst = r.id & 0xFFFFFFFF
+        with torch.cuda.stream(stream):
+            if r.kind == "metropolis":
+                api.resample_metropolis(st["lw"], r.B, r.seed, inst, anc=st["anc"],
+                                        status=st["status"])
+            else:
+                fn = api.resample_stratified if r.kind == "stratified" else api.resample_systematic
+                fn(st["lw"], r.seed, inst, anc=st["anc"], ws=self.single_ws[s],
+                   status=st["status"])
+            if r.D:
+                api.permute_copy(st["anc"], st["x_in"], x_out=st["x_out"], status=st["status"])
+            ev = torch.cuda.Event(enable_timing=True)
+            ev.record(stream)
+        return (None, ev)
 
     def poll(self, handle):
         return handle[1].query()
