@@ -244,38 +244,46 @@ __global__ __launch_bounds__(kTileThreads) void cumulative_kernel(const float *_
         m = ws.h->m;
         W = ws.h->W;
     }
+    // Every boundary this block needs is read before the flags are tested
+    // (all reads stay inside the arrays; the values are used only when the
+    // flags are clear), so the reads overlap instead of following each other.
+    const int64_t Pp = part_size(P), S = sub_stride(P), ns = sub_per_part(P);
+    const int xt = (int)(t * kTile / Pp);  // a part is whole tiles
+    const int parts = (int)((P + Pp - 1) / Pp);
+    const double Blo = t > 0 ? bound[t - 1] : 0.0, Bhi = bound[t];
+    double plo, phi;
+    part_range(bound, P, xt, &plo, &phi);
+    double lo[kParts];
+#pragma unroll
+    for (int y = 1; y < kParts; ++y)
+        lo[y] = y < parts ? bound[y * Pp / kTile - 1] : (double)INFINITY;
     if (flags) {
         const int64_t base = t * kTile + 4 * (int64_t)threadIdx.x;
         for (int k = 0; k < 4; ++k)
             if (base + k < P) C[base + k] = (double)NAN;
         return;
     }
-    const double Blo = t > 0 ? bound[t - 1] : 0.0;
     double w[4], Cv[4];
     tile_weights(v, m, w);
-    tile_cumulative(w, Blo, bound[t], Cs, Cv);
+    tile_cumulative(w, Blo, Bhi, Cs, Cv);
     store_cumw(C, P, t, Cv);
-    const int64_t Pp = part_size(P), S = sub_stride(P), ns = sub_per_part(P);
     // the group ends of this tile, and their guide entries: group g writes
     // guide[q] = g for the buckets q in (bucket(end[g - 1]), bucket(end[g])],
     // the part's last group also (bucket(end[last]), nb]; so guide[q] is the
     // first group whose end lies in bucket q or later and every entry is
     // written once. A group's predecessor end is in this tile's Cs or is an
     // earlier tile's last C', which equals that tile's bound bit for bit.
-    const int xt = (int)(t * kTile / Pp);  // a part is whole tiles
-    double plo, phi;
-    part_range(bound, P, xt, &plo, &phi);
     const Buckets bk = make_buckets(plo, phi, (int)((min((xt + 1) * Pp, P) - xt * Pp + S - 1) / S));
     uint16_t *guide = ws.guide + xt * guide_stride(P);
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        const int64_t e = t * kTile + 4 * (int64_t)threadIdx.x + m;
+    for (int mm = 0; mm < 4; ++mm) {
+        const int64_t e = t * kTile + 4 * (int64_t)threadIdx.x + mm;
         if (e >= P) break;
         const int64_t local = e - xt * Pp, end = min((xt + 1) * Pp, P);
         if ((local + 1) % S == 0 || e == end - 1) {
             const int64_t g = local / S;
-            ws.sub[xt * ns + g] = Cv[m];
-            const int bg = bk.of(Cv[m]);
+            ws.sub[xt * ns + g] = Cv[mm];
+            const int bg = bk.of(Cv[mm]);
             int bp = -1;
             if (g > 0) {
                 const int64_t pe = xt * Pp + g * S - 1;
@@ -289,11 +297,6 @@ __global__ __launch_bounds__(kTileThreads) void cumulative_kernel(const float *_
     // blocks per thread): part y holds C' in [B_{y Pp / kTile - 1}, the next
     // part's bound), so the search reads one byte per draw instead of redrawing.
     const double capW = below(W);
-    const int parts = (int)((P + Pp - 1) / Pp);
-    double lo[kParts];
-#pragma unroll
-    for (int y = 1; y < kParts; ++y)
-        lo[y] = y < parts ? bound[y * Pp / kTile - 1] : (double)INFINITY;
     uint32_t ids = 0;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
