@@ -419,7 +419,7 @@ __global__ __launch_bounds__(kSearchThreads) void multinomial_search_kernel(
     const int64_t rank = blockIdx.x / kParts, K = gridDim.x / kParts;
     const int64_t Pp = part_size(P), S = sub_stride(P), ns = sub_per_part(P);
     const int64_t start = part * Pp, end = min(start + Pp, P);
-    // this block's draws [d0, d1), a multiple of 16 wide
+    // this block's draws [d0, d1), a multiple of kIdsPerThread wide
     const int64_t span = ((P + K - 1) / K + kIdsPerThread - 1) / kIdsPerThread * kIdsPerThread;
     const int64_t d0 = min(P, rank * span), d1 = min(P, d0 + span);
     // every global read of the set-up is issued before the first wait: the
