@@ -127,10 +127,19 @@ def main():
                 "step": lambda bs, k: step(bs, k, 0)}[args.only]
         for bs in sets:
             rs.resample_stratified(bs["lw"], 1, 0, anc=bs["anc"], ws=ws)
-        for k in range(args.warmup + args.steps):
+        for k in range(args.warmup):
             only(sets[k % len(sets)], k)
+        # HIP events around the timed calls (back to back on one stream), so a
+        # profiler's per-kernel average can be set beside the same run's
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for k in range(args.warmup, args.warmup + args.steps):
+            only(sets[k % len(sets)], k)
+        e1.record()
         torch.cuda.synchronize()
-        print(f"profiled {args.only}: {args.warmup + args.steps} calls", flush=True)
+        us = e0.elapsed_time(e1) * 1e3 / max(args.steps, 1)
+        print(f"profiled {args.only}: {args.warmup + args.steps} calls; {us:.2f} us per timed call "
+              f"(HIP events, {args.steps} calls)", flush=True)
         return
 
     G = Graphs(torch)
