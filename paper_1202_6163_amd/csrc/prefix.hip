@@ -28,7 +28,7 @@
 // unsorted, so that resampler stores C (launch 3m) and searches it per draw
 // (launch 4m): the particles are split in eight parts, one per XCD, each
 // searched by the blocks that XCD runs (every 16th C' of the part staged in
-// LDS, then one 128-byte line of C). Up to 64 tiles the cumulative blocks
+// LDS, then one 128-byte line of C). Up to 1024 tiles the cumulative blocks
 // rebuild the boundaries themselves (no table launch); up to two tiles one
 // block does the whole multinomial resampling in one launch.
 //
@@ -198,7 +198,10 @@ __device__ __forceinline__ void fill_guide(uint16_t *guide, int from, int to, ui
 // C' of every sub_stride(P)-particle group of each part (the last group of a
 // part ends at the part's end) and the guide entries those groups own; and
 // the part byte of each of the tile's draws.
-// With FUSED (at most kFusedTableTiles tiles) there is no table launch: every
+// Up to this many tiles the cumulative blocks rebuild the boundaries themselves.
+constexpr int64_t kFusedCumulativeTiles = 1024;
+
+// With FUSED (at most kFusedCumulativeTiles tiles) there is no table launch: every
 // block rebuilds the tile boundaries in LDS from the tile sums (the same
 // function and order as the table launch, so the same bits), writes its own
 // tile's boundary for the search, and block 0 writes the header.
@@ -210,7 +213,7 @@ __global__ __launch_bounds__(kTileThreads) void cumulative_kernel(const float *_
                                                                   int32_t *status)
 {
     __shared__ double Cs[kTile];
-    __shared__ double sh_bound[FUSED ? kFusedTableTiles : 1];
+    __shared__ double sh_bound[FUSED ? kFusedCumulativeTiles : 1];
     const WsView ws = ws_view(ws_raw, P);
     const int64_t t = blockIdx.x;
     float v[4];
@@ -660,7 +663,7 @@ int launch_prefix(int kind, const float *lw, int32_t *anc, int32_t *off, int64_t
         break;
     case kMultinomial: {
         double *C = cumw ? cumw : reinterpret_cast<double *>(w + ws_layout(P, true).cumw);
-        if (n <= kFusedTableTiles) {
+        if (n <= kFusedCumulativeTiles) {
             hipLaunchKernelGGL(cumulative_kernel<true>, dim3((uint32_t)n), tb, 0, stream, lw, P, C,
                                w, seed, instance, status);
         } else {
