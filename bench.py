@@ -4,8 +4,9 @@ Step (the timed unit): one pass of the whole resampling path over one batch
 of P = 2^20 particles with log-weights N(0, sigma^2) (sigma = 1) and D = 4
 binary32 state rows: the Metropolis (B = 32), stratified, systematic and
 multinomial resamplers, each in the paper's output form (offspring for
-stratified and systematic, ancestors for the other two) and each followed by
-the ancestor-indexed state copy. Every step uses the next of several rotating
+stratified and systematic, written in the same pass as the ancestors the copy
+needs; ancestors for the other two) and each followed by the
+ancestor-indexed state copy. Every step uses the next of several rotating
 input/output buffer sets whose total exceeds the 256 MB Infinity Cache, so
 the step reads its inputs from HBM. value = resampled particles per second
 (4 P per step) at the p99 step time.
@@ -17,6 +18,15 @@ Beside it the JSON line carries:
                 (Metropolis at each B), with and without the copy, the
                 accuracy metric sum_i (o_i/P - w_i/W)^2, the ESS, eq. (5)'s B
                 and the Metropolis-vs-stratified crossover (warm cache);
+  dirichlet     Sec. 3's experiment: Dirichlet weights, P = 256 .. 65536,
+                error and per-call time of every resampler and the
+                sorted-weight variants;
+  batched       1024 independent instances in one batched launch against
+                per-instance calls;
+  filter        the bootstrap filter (P = 2^18, D = 8, T = 200) against the
+                Kalman log-likelihood;
+  pmcmc         particle marginal Metropolis-Hastings with batched filters;
+  serving       Poisson arrivals at 2000 req/s: latency percentiles;
   cpu_baseline  the CPU oracle on a bounded sample of the same step.
 """
 import argparse
