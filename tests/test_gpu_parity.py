@@ -299,11 +299,18 @@ def test_multinomial_beyond_one_line_groups(rs, P):
     explained_mismatches("multinomial", anc_g, anc_o, C_o, seed, inst)
 
 
+# (equal-weight size, zero-weight case size, zero run, single-weight size):
+# the one-block multinomial path (at most 2048 particles) and the others
+EDGE_CASES = [(5000, 6000, (1024, 3072), 3000), (1500, 1800, (256, 1024), 1000)]
+
+
 @pytest.mark.parametrize("kind", PREFIX)
-def test_prefix_edge_weights(rs, kind):
+@pytest.mark.parametrize("case", EDGE_CASES)
+def test_prefix_edge_weights(rs, kind, case):
+    P_eq, P_zero, (z0, z1), P_one = case
     fn = getattr(rs, f"resample_{kind}")
     # equal weights: identity for stratified / systematic
-    P = 5000
+    P = P_eq
     eq = np.full(P, 1.5, dtype=np.float32)
     anc_o, _ = ORACLE_FN[kind](eq, 1, 0)
     anc_g = host(fn(dev(eq), 1, 0))
@@ -311,9 +318,9 @@ def test_prefix_edge_weights(rs, kind):
         assert np.array_equal(anc_g, np.arange(P))
     assert np.array_equal(anc_g, anc_o)
     # zero weights (-inf) inside, at the ends and filling whole tiles
-    lw = workloads.normal_logweights(6000, 1.0, 2)
+    lw = workloads.normal_logweights(P_zero, 1.0, 2)
     lw[:5] = -np.inf
-    lw[1024:3072] = -np.inf
+    lw[z0:z1] = -np.inf
     lw[-7:] = -np.inf
     anc_o, _, C_o = ORACLE_FN[kind](lw, 3, 0, want_cumw=True)
     C = torch.empty(lw.size, dtype=torch.float64, device="cuda")
@@ -327,9 +334,9 @@ def test_prefix_edge_weights(rs, kind):
     if kw:
         check_offspring(host(kw["off"]), anc_g)
     # a single finite weight takes every draw
-    one = np.full(3000, -np.inf, dtype=np.float32)
-    one[2999] = 0.25
-    assert np.all(host(fn(dev(one), 1, 0)) == 2999)
+    one = np.full(P_one, -np.inf, dtype=np.float32)
+    one[P_one - 1] = 0.25
+    assert np.all(host(fn(dev(one), 1, 0)) == P_one - 1)
 
 
 # sizes for the three launch structures: one block (multinomial up to two
