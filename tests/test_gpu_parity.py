@@ -134,6 +134,17 @@ def test_metropolis_full_size(rs, B, sigma):
         assert np.array_equal(anc[idx], ref)
 
 
+def test_metropolis_beyond_2_20(rs):
+    # a size above the benchmark's, not a power of two: the general index
+    # map (high word of r P) over five million chains, weights far beyond L2
+    P, B, seed, inst = 5_000_003, 8, 11, 4
+    lw = workloads.normal_logweights(P, 1.0, seed)
+    say("metropolis P =", P, "B =", B)
+    anc = host(rs.resample_metropolis(dev(lw), B, seed, inst))
+    ref, _ = oracle.metropolis(lw, B, seed, inst)
+    assert np.array_equal(anc, ref)
+
+
 @pytest.mark.parametrize("P,sigma", [(1000, 0.5), (4097, 2.0), (1 << 18, 1.0)])
 def test_metropolis_adaptive_B(rs, P, sigma):
     lw = workloads.normal_logweights(P, sigma, 11)
