@@ -40,9 +40,11 @@ __device__ __forceinline__ void normals(uint64_t seed, uint32_t i, uint32_t t, i
             const double u1 = ((double)r[2 * pair] + 0.5) * 0x1p-32;
             const double u2 = (double)r[2 * pair + 1] * 0x1p-32;
             const double rad = sqrt(-2.0 * log(u1));
+            double sn, cs;
+            sincos(two_pi * u2, &sn, &cs);  // one argument reduction for both
             const int d0 = 4 * h + 2 * pair;
-            if (d0 < D) z[d0] = rad * cos(two_pi * u2);
-            if (d0 + 1 < D) z[d0 + 1] = rad * sin(two_pi * u2);
+            if (d0 < D) z[d0] = rad * cs;
+            if (d0 + 1 < D) z[d0 + 1] = rad * sn;
         }
     }
 }
