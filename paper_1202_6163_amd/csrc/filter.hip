@@ -29,22 +29,31 @@ namespace {
 constexpr int kFilterThreads = 256;
 constexpr int kMaxD = 64;
 
-__device__ __forceinline__ void normals(uint64_t seed, uint32_t i, uint32_t t, int D, double *z)
+// One Box-Muller pair from two Philox words.
+__device__ __forceinline__ void box_muller(uint32_t ra, uint32_t rb, double *z0, double *z1)
 {
     const double two_pi = 6.283185307179586476925286766559;
+    const double u1 = ((double)ra + 0.5) * 0x1p-32;
+    const double u2 = (double)rb * 0x1p-32;
+    const double rad = sqrt(-2.0 * log(u1));
+    double sn, cs;
+    sincos(two_pi * u2, &sn, &cs);  // one argument reduction for both
+    *z0 = rad * cs;
+    *z1 = rad * sn;
+}
+
+__device__ __forceinline__ void normals(uint64_t seed, uint32_t i, uint32_t t, int D, double *z)
+{
     for (int h = 0; 4 * h < D; ++h) {
         const Block4 b = philox(seed, i, t, (uint32_t)h, kTagFilterNoise);
         const uint32_t r[4] = {b.r0, b.r1, b.r2, b.r3};
 #pragma unroll
         for (int pair = 0; pair < 2; ++pair) {
-            const double u1 = ((double)r[2 * pair] + 0.5) * 0x1p-32;
-            const double u2 = (double)r[2 * pair + 1] * 0x1p-32;
-            const double rad = sqrt(-2.0 * log(u1));
-            double sn, cs;
-            sincos(two_pi * u2, &sn, &cs);  // one argument reduction for both
+            double z0, z1;
+            box_muller(r[2 * pair], r[2 * pair + 1], &z0, &z1);
             const int d0 = 4 * h + 2 * pair;
-            if (d0 < D) z[d0] = rad * cs;
-            if (d0 + 1 < D) z[d0 + 1] = rad * sn;
+            if (d0 < D) z[d0] = z0;
+            if (d0 + 1 < D) z[d0 + 1] = z1;
         }
     }
 }
@@ -74,7 +83,6 @@ __global__ __launch_bounds__(kFilterThreads) void propagate_weight_kernel(
     for (int k = threadIdx.x; k < D * D; k += kFilterThreads) sA[k] = A[k];
     for (int k = threadIdx.x; k < D; k += kFilterThreads) sy[k] = (double)y[k];
     __syncthreads();
-    double z[DC > 0 ? DC : kMaxD];
     double xv[DC > 0 ? DC : kMaxD];
     for (int64_t g = blockIdx.x * (int64_t)kFilterThreads + threadIdx.x; g < K * P;
          g += (int64_t)gridDim.x * kFilterThreads) {
@@ -90,16 +98,34 @@ __global__ __launch_bounds__(kFilterThreads) void propagate_weight_kernel(
         } else {
             for (int d = 0; d < D; ++d) xv[d] = (double)xi[d];
         }
-        normals(seed + (uint64_t)k, (uint32_t)i, t, D, z);
+        // each noise pair is drawn just before the two rows that use it, so
+        // only two noise values are live (all D at once, with the inlined
+        // binary64 log and sincos, took over 250 VGPRs: one wave per SIMD)
         double ss = 0.0;
         float out[DC > 0 ? DC : kMaxD];
-        for (int a = 0; a < D; ++a) {
-            double acc = 0.0;
-            for (int b = 0; b < D; ++b) acc += sA[a * D + b] * xv[b];
-            const float xa = (float)(acc + sqk * z[a]);
-            out[a] = xa;
-            const double e = sy[a] - (double)xa;
-            ss += e * e;
+        for (int h = 0; 4 * h < D; ++h) {
+            const Block4 bl = philox(seed + (uint64_t)k, (uint32_t)i, t, (uint32_t)h,
+                                     kTagFilterNoise);
+            const uint32_t rw[4] = {bl.r0, bl.r1, bl.r2, bl.r3};
+#pragma unroll
+            for (int pair = 0; pair < 2; ++pair) {
+                const int d0 = 4 * h + 2 * pair;
+                if (d0 >= D) break;
+                double zp[2];
+                box_muller(rw[2 * pair], rw[2 * pair + 1], &zp[0], &zp[1]);
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const int a = d0 + e;
+                    if (a < D) {
+                        double acc = 0.0;
+                        for (int b = 0; b < D; ++b) acc += sA[a * D + b] * xv[b];
+                        const float xa = (float)(acc + sqk * zp[e]);
+                        out[a] = xa;
+                        const double ev = sy[a] - (double)xa;
+                        ss += ev * ev;
+                    }
+                }
+            }
         }
         float *xo = x_out + g * D;
         if (DC > 0 && DC % 4 == 0) {
