@@ -63,3 +63,59 @@ def test_filter_small_matches_oracle_in_distribution():
     o = np.array([oracle.bootstrap_filter(A, y, 2048, 0.1, 0.5, seed=s) for s in range(12)])
     se = np.sqrt(g.var(ddof=1) / 12 + o.var(ddof=1) / 12)
     assert abs(g.mean() - o.mean()) <= 4 * se + 0.02
+
+
+@pytest.mark.parametrize("resampler", ["stratified", "systematic", "multinomial", "metropolis",
+                                       "metropolis_adaptive"])
+def test_filter_factors_equal_hand_issued_sequence(rs, resampler):
+    # The filter's steps issued by hand through the library, in order, give
+    # the same per-step likelihood factors bit for bit as the filter run
+    # eagerly and as every replay of its captured run (with eager work and
+    # syncs between replays).
+    from paper_1202_6163_amd.filter import BootstrapFilter
+    A = workloads.filter_model(D=8, seed=0)
+    y = workloads.filter_observations(A, T=20, seed=3)
+    P, seed, B = 1 << 16, 4, 2048
+    yd = torch.as_tensor(y, dtype=torch.float32).contiguous().cuda()
+
+    x = torch.empty((P, 8), dtype=torch.float32, device="cuda")
+    xp, lw = torch.empty_like(x), torch.empty(P, dtype=torch.float32, device="cuda")
+    anc = torch.empty(P, dtype=torch.int32, device="cuda")
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    B_used = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ws = rs.workspace(P, rs.MULTINOMIAL, "cuda")
+    ref = torch.empty(y.shape[0], dtype=torch.float64, device="cuda")
+    rs.filter_init(x, seed)
+    for t in range(1, y.shape[0] + 1):
+        rs.filter_propagate_weight(x, torch.as_tensor(A).cuda(), yd[t - 1], 0.1, 0.5, seed, t,
+                                   x_out=xp, lw=lw)
+        if resampler == "metropolis":
+            rs.rs_log_sum_exp(lw, out=ref[t - 1:t], ws=ws, status=status)
+            rs.resample_and_copy("metropolis", lw, xp, seed, t, B=B, anc=anc, x_out=x,
+                                 status=status)
+            continue
+        if resampler == "metropolis_adaptive":
+            rs.resample_metropolis_adaptive(lw, seed, t, eps=0.01, B_max=B, anc=anc,
+                                            B_used=B_used, ws=ws, status=status)
+            rs.permute_copy(anc, xp, x_out=x, status=status)
+        else:
+            rs.resample_and_copy(resampler, lw, xp, seed, t, anc=anc, x_out=x, ws=ws,
+                                 status=status)
+        rs.rs_workspace_log_sum_exp(ws, P, out=ref[t - 1:t])
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0
+    want = ref.cpu().numpy()
+
+    f = BootstrapFilter(A, P, seed=seed, resampler=resampler, B=B)
+    got = torch.empty_like(ref)
+    f._run(yd, got)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(got.cpu().numpy(), want)
+    g = f.capture(yd, got)
+    for _ in range(3):
+        got.fill_(0.0)
+        g.replay()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(got.cpu().numpy(), want)
+        xp.add_(1.0)  # eager work between replays
+        torch.cuda.synchronize()
