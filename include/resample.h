@@ -18,7 +18,8 @@
  *  - P = 0 is an empty resampling: RS_OK, nothing is launched or touched.
  *  - Argument errors are returned synchronously, before any launch:
  *      RS_EINVAL     null pointer, P < 0, P > 2^31 - 1, D < 1, overlapping
- *                    input and output buffers, unknown resampler kind;
+ *                    input and output buffers, unknown resampler kind, a
+ *                    workspace not 256-byte aligned (hipMalloc's blocks are);
  *      RS_EWORKSPACE workspace smaller than rs_workspace_bytes();
  *      RS_EHIP       a HIP launch failed (hipGetLastError after the launch).
  *  - Data errors are reported asynchronously: bits RS_FLAG_* are OR-ed into the

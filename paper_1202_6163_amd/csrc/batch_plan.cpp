@@ -130,6 +130,7 @@ int rs_batch_plan_init(rs_batch_plan *plan, const rs_instance *descs, int32_t n,
     if (plan_bytes < L.bytes) return RS_EWORKSPACE;
     const size_t need_ws = rs_batch_workspace_bytes(descs, n);
     if (need_ws > 0 && (!ws || ws_bytes < need_ws)) return RS_EWORKSPACE;
+    if (need_ws > 0 && ((uintptr_t)ws & 255u)) return RS_EINVAL;  // 256-byte aligned sections
 
     std::vector<unsigned char> local;
     unsigned char *host = static_cast<unsigned char *>(host_staging);

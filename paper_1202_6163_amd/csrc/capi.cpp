@@ -93,6 +93,11 @@ bool overlaps(const void *a, size_t abytes, const void *b, size_t bbytes)
     return a0 < b0 + bbytes && b0 < a0 + abytes;
 }
 
+// Workspace sections start 256 bytes apart and are read with 16-byte vector
+// loads, so the workspace itself must start on a 256-byte boundary (as
+// hipMalloc's blocks do).
+bool misaligned(const void *ws) { return ((uintptr_t)ws & 255u) != 0; }
+
 int map_rc(int rc) { return rc == 0 ? RS_OK : (rc == -1 ? RS_EINVAL : RS_EHIP); }
 
 int prefix_call(int kind, const float *lw, int32_t *anc, int32_t *off, int64_t P, uint64_t seed,
@@ -100,7 +105,7 @@ int prefix_call(int kind, const float *lw, int32_t *anc, int32_t *off, int64_t P
                 hipStream_t stream)
 {
     if (P == 0) return RS_OK;
-    if (!lw || (!anc && !off) || !ws || P < 0 || P > kMaxP) return RS_EINVAL;
+    if (!lw || (!anc && !off) || !ws || misaligned(ws) || P < 0 || P > kMaxP) return RS_EINVAL;
     if (off && kind == rs::kMultinomial) return RS_EINVAL;
     const size_t p = (size_t)P;
     const void *outs[3] = {anc, off, cumw};
@@ -221,7 +226,7 @@ int resample_and_copy(int kind, const float *lw, int32_t *anc, int32_t *off, int
         const rs::MetropolisTuning t = current_tuning();
         return map_rc(rs::launch_metropolis(lw, anc, P, B, seed, instance, status, t, stream, r));
     }
-    if (!ws) return RS_EINVAL;
+    if (!ws || misaligned(ws)) return RS_EINVAL;
     if (ws_bytes < rs_workspace_bytes(P, kind)) return RS_EWORKSPACE;
     if (overlaps(ws, ws_bytes, lw, 4 * p) || overlaps(ws, ws_bytes, x_in, rows)) return RS_EINVAL;
     for (int a = 0; a < 3; ++a)
@@ -232,7 +237,7 @@ int resample_and_copy(int kind, const float *lw, int32_t *anc, int32_t *off, int
 
 int rs_workspace_log_sum_exp(const void *ws, int64_t P, double *out, hipStream_t stream)
 {
-    if (!ws || !out || P < 1 || P > kMaxP) return RS_EINVAL;
+    if (!ws || misaligned(ws) || !out || P < 1 || P > kMaxP) return RS_EINVAL;
     return map_rc(rs::launch_workspace_lse(ws, P, out, stream));
 }
 
@@ -249,7 +254,7 @@ int resample_sorted(int kind, const float *lw, int32_t *anc, int64_t P, uint64_t
 {
     if (kind != RS_STRATIFIED && kind != RS_SYSTEMATIC && kind != RS_MULTINOMIAL) return RS_EINVAL;
     if (P == 0) return RS_OK;
-    if (!lw || !anc || !ws || P < 0 || P > kMaxP) return RS_EINVAL;
+    if (!lw || !anc || !ws || misaligned(ws) || P < 0 || P > kMaxP) return RS_EINVAL;
     const size_t p = (size_t)P;
     if (overlaps(lw, 4 * p, anc, 4 * p)) return RS_EINVAL;
     if (ws_bytes < rs_sorted_workspace_bytes(P, kind)) return RS_EWORKSPACE;
@@ -281,7 +286,7 @@ int permute_copy(const int32_t *anc, const float *x_in, float *x_out, int64_t P,
 int rs_log_sum_exp(const float *lw, int64_t P, double *out, void *ws, size_t ws_bytes,
                    int32_t *status, hipStream_t stream)
 {
-    if (!lw || !out || !ws || P < 1 || P > kMaxP) return RS_EINVAL;
+    if (!lw || !out || !ws || misaligned(ws) || P < 1 || P > kMaxP) return RS_EINVAL;
     if (ws_bytes < rs_workspace_bytes(P, RS_LOG_SUM_EXP)) return RS_EWORKSPACE;
     return map_rc(rs::launch_log_sum_exp(lw, P, out, ws, status, stream));
 }
@@ -297,7 +302,8 @@ int resample_metropolis_adaptive(const float *lw, int32_t *anc, int64_t P, doubl
                                  hipStream_t stream)
 {
     if (P == 0) return RS_OK;
-    if (!lw || !anc || !ws || P < 0 || P > kMaxP || !(eps > 0.0)) return RS_EINVAL;
+    if (!lw || !anc || !ws || misaligned(ws) || P < 0 || P > kMaxP || !(eps > 0.0))
+        return RS_EINVAL;
     if (overlaps(lw, 4 * (size_t)P, anc, 4 * (size_t)P)) return RS_EINVAL;
     if (ws_bytes < rs_workspace_bytes(P, RS_METROPOLIS_ADAPTIVE)) return RS_EWORKSPACE;
     if (overlaps(ws, ws_bytes, lw, 4 * (size_t)P) || overlaps(ws, ws_bytes, anc, 4 * (size_t)P))

@@ -289,7 +289,20 @@ __device__ inline TableSums boundaries(const WsView &ws, int64_t P, double *boun
     float m = -INFINITY;
     float mt[kRegTiles];
     double S[kRegTiles];
-    if (reg) {
+    if (reg && t1 - t0 == kRegTiles) {
+        // a whole run: 16-byte loads (the sections are 256-byte aligned and
+        // t0 is a multiple of kRegTiles here)
+        static_assert(kRegTiles == 4, "one float4 of maxima, two double2 of sums");
+        const float4 m4 = *reinterpret_cast<const float4 *>(ws.tile_max + t0);
+        const double2 s01 = *reinterpret_cast<const double2 *>(ws.tile_sum + t0);
+        const double2 s23 = *reinterpret_cast<const double2 *>(ws.tile_sum + t0 + 2);
+        const int4 f4 = *reinterpret_cast<const int4 *>(ws.tile_flags + t0);
+        mt[0] = m4.x, mt[1] = m4.y, mt[2] = m4.z, mt[3] = m4.w;
+        S[0] = s01.x, S[1] = s01.y, S[2] = s23.x, S[3] = s23.y;
+        fl = f4.x | f4.y | f4.z | f4.w;
+#pragma unroll
+        for (int k = 0; k < kRegTiles; ++k) m = fmaxf(m, mt[k]);
+    } else if (reg) {
 #pragma unroll
         for (int k = 0; k < kRegTiles; ++k) {
             const int64_t t = t0 + k;

@@ -209,6 +209,35 @@ def test_probe_argument_errors(L):
     assert lib.rs_probe_philox(1, 256, 1, None, None) == L.RS_EINVAL
 
 
+def test_workspace_must_be_256_byte_aligned(L):
+    # a workspace off a 256-byte boundary is refused before any launch, by
+    # every entry point that takes one (with a large enough size, so the
+    # alignment is the only fault)
+    lib = L.lib
+    f = ctypes.c_void_p
+    lw, anc, xi, xo, out = f(0x100000), f(0x200000), f(0x400000), f(0x800000), f(0xA00000)
+    big = 1 << 30
+    for bad in (f(0xC00008), f(0xC00080)):
+        for fn in (lib.resample_stratified, lib.resample_systematic):
+            assert fn(lw, anc, None, 10, 1, 0, None, bad, big, None, None) == L.RS_EINVAL
+        assert lib.resample_multinomial(lw, anc, 10, 1, 0, None, bad, big, None,
+                                        None) == L.RS_EINVAL
+        for kind in (L.STRATIFIED, L.SYSTEMATIC, L.MULTINOMIAL):
+            assert lib.resample_and_copy(kind, lw, anc, None, 10, 8, 1, 0, xi, xo, 4, bad, big,
+                                         None, None) == L.RS_EINVAL
+            assert lib.resample_sorted(kind, lw, anc, 10, 1, 0, bad, big, None,
+                                       None) == L.RS_EINVAL
+        assert lib.rs_log_sum_exp(lw, 10, out, bad, big, None, None) == L.RS_EINVAL
+        assert lib.rs_workspace_log_sum_exp(bad, 10, out, None) == L.RS_EINVAL
+        assert lib.resample_metropolis_adaptive(lw, anc, 10, 0.01, 64, 1, 0, bad, big, None,
+                                                None, None) == L.RS_EINVAL
+    # the same calls with an aligned workspace get past the check (to the size test)
+    good = f(0xC00000)
+    assert lib.resample_multinomial(lw, anc, 10, 1, 0, None, good, 8, None,
+                                    None) == L.RS_EWORKSPACE
+    assert lib.rs_log_sum_exp(lw, 10, out, good, 8, None, None) == L.RS_EWORKSPACE
+
+
 def test_sorted_variant_arguments(L):
     lib = L.lib
     f = ctypes.c_void_p
