@@ -94,44 +94,103 @@ __device__ __forceinline__ double unit53(uint32_t a, uint32_t b)
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
 __device__ __forceinline__ int wave_id() { return (int)(threadIdx.x / kWave); }
 
-__device__ __forceinline__ double wave_inclusive_sum(double v)
+// Lane moves by DPP (GFX9 controls): the source lane is read inside the VALU
+// instruction, with no LDS round trip as a ds_bpermute shuffle takes. A lane
+// whose source lies outside the pattern, or in a row the row mask leaves
+// out, receives `fill`. Wave ops below run in uniform control flow (all 64
+// lanes active).
+constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114,
+              kDppRowShr8 = 0x118, kDppWaveShr1 = 0x138, kDppRowBcast15 = 0x142,
+              kDppRowBcast31 = 0x143;
+
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v, uint32_t fill)
 {
-    const int lane = lane_id();
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        double y = __shfl_up(v, off, kWave);
-        if (lane >= off) v += y;
-    }
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)fill, (int)v, CTRL, ROW_MASK, 0xf, false);
+}
+
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t v, uint64_t fill)
+{
+    const uint64_t lo = dpp_u32<CTRL, ROW_MASK>((uint32_t)v, (uint32_t)fill);
+    const uint64_t hi = dpp_u32<CTRL, ROW_MASK>((uint32_t)(v >> 32), (uint32_t)(fill >> 32));
+    return (hi << 32) | lo;
+}
+
+template <int CTRL, int ROW_MASK = 0xf, typename T>
+__device__ __forceinline__ T dpp_move(T v, T fill)
+{
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit lanes");
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(T, dpp_u64<CTRL, ROW_MASK>(__builtin_bit_cast(uint64_t, v),
+                                                             __builtin_bit_cast(uint64_t, fill)));
+    else
+        return __builtin_bit_cast(T, dpp_u32<CTRL, ROW_MASK>(__builtin_bit_cast(uint32_t, v),
+                                                             __builtin_bit_cast(uint32_t, fill)));
+}
+
+// Inclusive scan over the 64 lanes with an associative op and its identity:
+// Hillis-Steele inside each row of 16 lanes (shifts 1, 2, 4, 8), then row
+// 0's total into row 1 and row 2's into row 3, then rows 0-1's total into
+// rows 2 and 3. A fixed order, so the same bits on every call.
+template <typename T, typename Op>
+__device__ __forceinline__ T wave_scan(T v, T id, Op op)
+{
+    v = op(v, dpp_move<kDppRowShr1>(v, id));
+    v = op(v, dpp_move<kDppRowShr2>(v, id));
+    v = op(v, dpp_move<kDppRowShr4>(v, id));
+    v = op(v, dpp_move<kDppRowShr8>(v, id));
+    v = op(v, dpp_move<kDppRowBcast15, 0xa>(v, id));
+    v = op(v, dpp_move<kDppRowBcast31, 0xc>(v, id));
     return v;
 }
 
-__device__ __forceinline__ double wave_sum(double v)
+// Lane 63's value, in every lane.
+__device__ __forceinline__ double lane63(double v)
 {
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-    return v;
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint64_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, 63);
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), 63);
+    return __longlong_as_double((long long)((hi << 32) | lo));
 }
+__device__ __forceinline__ float lane63(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+__device__ __forceinline__ int lane63(int v) { return __builtin_amdgcn_readlane(v, 63); }
+
+struct AddOp { template <typename T> __device__ T operator()(T a, T b) const { return a + b; } };
+struct MaxOp {
+    __device__ float operator()(float a, float b) const { return fmaxf(a, b); }
+    __device__ double operator()(double a, double b) const { return fmax(a, b); }
+};
+struct OrOp { __device__ int operator()(int a, int b) const { return a | b; } };
+
+__device__ __forceinline__ double wave_inclusive_sum(double v) { return wave_scan(v, 0.0, AddOp{}); }
+
+// Inclusive prefix maximum of non-negative values (0 is the identity).
+__device__ __forceinline__ double wave_inclusive_max_nonneg(double v)
+{
+    return wave_scan(v, 0.0, MaxOp{});
+}
+
+// Each lane gets its left neighbour's value, lane 0 gets 0.
+template <typename T>
+__device__ __forceinline__ T wave_shift_up(T v) { return dpp_move<kDppWaveShr1>(v, (T)0); }
+
+__device__ __forceinline__ double wave_sum(double v) { return lane63(wave_scan(v, 0.0, AddOp{})); }
 
 __device__ __forceinline__ float wave_max(float v)
 {
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, kWave));
-    return v;
+    return lane63(wave_scan(v, -(float)INFINITY, MaxOp{}));
 }
 
 __device__ __forceinline__ double wave_max(double v)
 {
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, kWave));
-    return v;
+    return lane63(wave_scan(v, -(double)INFINITY, MaxOp{}));
 }
 
-__device__ __forceinline__ int wave_or(int v)
-{
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) v |= __shfl_xor(v, off, kWave);
-    return v;
-}
+__device__ __forceinline__ int wave_or(int v) { return lane63(wave_scan(v, 0, OrOp{})); }
 
 // Largest binary64 strictly below a positive finite b.
 __device__ __forceinline__ double below(double b)

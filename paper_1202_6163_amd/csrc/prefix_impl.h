@@ -57,8 +57,7 @@ __device__ inline double block_exclusive_sum(double v, double *red)
 {
     const int lane = lane_id(), wave = wave_id();
     const double incl = wave_inclusive_sum(v);
-    double excl = __shfl_up(incl, 1, kWave);
-    if (lane == 0) excl = 0.0;
+    const double excl = wave_shift_up(incl);
     if (lane == kWave - 1) red[wave] = incl;
     __syncthreads();
     double wp = 0.0;
@@ -71,14 +70,8 @@ __device__ inline double block_exclusive_sum(double v, double *red)
 __device__ inline double block_exclusive_max(double v, double *red)
 {
     const int lane = lane_id(), wave = wave_id();
-    double incl = v;
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        const double y = __shfl_up(incl, off, kWave);
-        if (lane >= off) incl = fmax(incl, y);
-    }
-    double excl = __shfl_up(incl, 1, kWave);
-    if (lane == 0) excl = 0.0;
+    const double incl = wave_inclusive_max_nonneg(v);
+    const double excl = wave_shift_up(incl);
     if (lane == kWave - 1) red[wave] = incl;
     __syncthreads();
     double wp = 0.0;
@@ -90,14 +83,8 @@ __device__ inline double block_exclusive_max(double v, double *red)
 __device__ inline int64_t block_exclusive_isum(int64_t v, int64_t *red, int64_t *total)
 {
     const int lane = lane_id(), wave = wave_id();
-    int64_t incl = v;
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        const int64_t y = __shfl_up(incl, off, kWave);
-        if (lane >= off) incl += y;
-    }
-    int64_t excl = __shfl_up(incl, 1, kWave);
-    if (lane == 0) excl = 0;
+    const int64_t incl = wave_scan(v, (int64_t)0, AddOp{});
+    const int64_t excl = wave_shift_up(incl);
     if (lane == kWave - 1) red[wave] = incl;
     __syncthreads();
     int64_t wp = 0, tot = 0;
