@@ -493,15 +493,10 @@ __global__ __launch_bounds__(kSearchThreads) void multinomial_search_kernel(
         pv1 = load_part_bytes(ws.part, i0 + kQueue + 16, d1);
         // (2) queue slots: a wave-wide prefix of the counts, one LDS atomic per wave
         const int cnt = __popc(keep);
-        int incl = cnt;
-#pragma unroll
-        for (int off = 1; off < kWave; off <<= 1) {
-            const int y = __shfl_up(incl, off, kWave);
-            if (lane >= off) incl += y;
-        }
+        const int incl = wave_scan(cnt, 0, AddOp{});
         int base = 0;
         if (lane == kWave - 1) base = atomicAdd(&sh_count[parity], incl);
-        base = __shfl(base, kWave - 1, kWave);
+        base = lane63(base);
         int pos = base + incl - cnt;
         while (keep) {
             const int bit = __ffs((int)keep) - 1;
