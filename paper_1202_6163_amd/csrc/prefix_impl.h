@@ -30,28 +30,6 @@ __device__ inline double block_sum(double v, double *red)
     return s;
 }
 
-__device__ inline float block_max(float v, float *red)
-{
-    v = wave_max(v);
-    if (lane_id() == 0) red[wave_id()] = v;
-    __syncthreads();
-    float s = red[0];
-    for (int w = 1; w < kNW; ++w) s = fmaxf(s, red[w]);
-    __syncthreads();
-    return s;
-}
-
-__device__ inline int block_or(int v, int *red)
-{
-    v = wave_or(v);
-    if (lane_id() == 0) red[wave_id()] = v;
-    __syncthreads();
-    int s = 0;
-    for (int w = 0; w < kNW; ++w) s |= red[w];
-    __syncthreads();
-    return s;
-}
-
 // Exclusive prefix sum over threads.
 __device__ inline double block_exclusive_sum(double v, double *red)
 {
@@ -226,8 +204,22 @@ __device__ inline void tile_reduce_body(const float *__restrict__ lw, int64_t P,
         if (isnan(v[k])) fl |= kFlagNan;
         else if (isinf(v[k]) && v[k] > 0.0f) fl |= kFlagPosInf;
     }
-    const float mx = block_max(fmaxf(fmaxf(v[0], v[1]), fmaxf(v[2], v[3])), redf);
-    fl = block_or(fl, redi);
+    // maximum and flags in one barrier (redf/redi are next written after the
+    // barriers of the sum below)
+    float mx = wave_max(fmaxf(fmaxf(v[0], v[1]), fmaxf(v[2], v[3])));
+    fl = wave_or(fl);
+    if (lane_id() == 0) {
+        redf[wave_id()] = mx;
+        redi[wave_id()] = fl;
+    }
+    __syncthreads();
+    mx = redf[0];
+    fl = redi[0];
+#pragma unroll
+    for (int w = 1; w < kNW; ++w) {
+        mx = fmaxf(mx, redf[w]);
+        fl |= redi[w];
+    }
     double s = 0.0;
     if (mx > -INFINITY) {
 #pragma unroll
