@@ -378,25 +378,60 @@ __device__ __forceinline__ uint4 load_part_bytes(const uint8_t *part, int64_t i0
     return *reinterpret_cast<const uint4 *>(part + (i0 < d1 ? i0 : 0));
 }
 
+// Orders a wave's LDS accesses around an exchange between its own lanes
+// (the compiler keeps them in program order; the hardware runs one wave's
+// LDS instructions in order).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // For each lane's draw (x, gbase) with coop set: the number of the 16 C' of
 // its group (one 128-byte line at C + gbase) that are <= x. Eight lanes read
 // a line together, 16 bytes each, so one load instruction covers eight whole
 // lines (the address unit then handles 8 lines per instruction, not 64); a
-// ballot per comparison gives each owner its line's count. Every lane of the
+// ballot per comparison gives each owner its line's count. Group grp (lanes
+// 8 grp .. 8 grp + 7) reads, in round r, the line of the draw owned by lane
+// 8 r + grp. The draws reach their readers through the wave's 768-byte LDS
+// exchange area (xw, gw): lane s writes to entry (s mod 8) * 8 + s / 8, so
+// the eight draws a group reads lie together and come back in six 16-byte
+// reads. Lanes without a cooperative draw read the line at C (the search runs
+// only for P > 2048, so C[0..15] exists) and count nothing. Every lane of the
 // wave must call this (lanes without a draw pass coop = false).
-__device__ __forceinline__ int line_count_coop(const double *C, double x, int64_t gbase, bool coop)
+__device__ __forceinline__ int line_count_coop(const double *C, double x, int64_t gbase, bool coop,
+                                               double *xw, int32_t *gw)
 {
     const int lane = lane_id(), grp = lane >> 3, sub = lane & 7;
-    double2 c[8];
+    const uint64_t coop_mask = __ballot(coop);
+    wave_lds_sync();  // the previous call's reads are done
+    xw[sub * 8 + grp] = x;
+    gw[sub * 8 + grp] = coop ? (int32_t)gbase : 0;
+    wave_lds_sync();
     double xs[8];
+    int32_t gs[8];
+    {
+        const double2 *xv = reinterpret_cast<const double2 *>(xw + grp * 8);
+        const int4 *gv = reinterpret_cast<const int4 *>(gw + grp * 8);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double2 d = xv[q];
+            xs[2 * q] = d.x;
+            xs[2 * q + 1] = d.y;
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int4 g = gv[q];
+            gs[4 * q] = g.x, gs[4 * q + 1] = g.y, gs[4 * q + 2] = g.z, gs[4 * q + 3] = g.w;
+        }
+    }
+    double2 c[8];
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
-        const int src = 8 * r + grp;  // the owner of the draw this group reads
-        xs[r] = __shfl(x, src, kWave);
-        const int64_t gs = __shfl(gbase, src, kWave);
-        const bool cs = __shfl((int)coop, src, kWave) != 0;
-        c[r] = cs ? reinterpret_cast<const double2 *>(C + gs)[sub]
-                  : make_double2((double)INFINITY, (double)INFINITY);
+        const double2 v = reinterpret_cast<const double2 *>(C + gs[r])[sub];
+        const bool cs = ((coop_mask >> (8 * r + grp)) & 1ull) != 0;
+        c[r] = cs ? v : make_double2((double)INFINITY, (double)INFINITY);
     }
     int cnt = 0;
 #pragma unroll
@@ -417,6 +452,8 @@ __global__ __launch_bounds__(kSearchThreads) void multinomial_search_kernel(
     __shared__ __align__(16) uint16_t sh_guide[kSubMax + 8];
     static_assert(kSubMax % 8 == 0, "guide rows are whole 16-byte vectors");
     __shared__ int32_t sh_count[2];
+    __shared__ __align__(16) double sh_xw[kSearchThreads];   // line_count_coop exchange,
+    __shared__ __align__(16) int32_t sh_gw[kSearchThreads];  // 64 entries per wave
     const WsView ws = ws_view(ws_raw, P);
     const int part = (int)(blockIdx.x % kParts);
     const int64_t rank = blockIdx.x / kParts, K = gridDim.x / kParts;
@@ -532,7 +569,10 @@ __global__ __launch_bounds__(kSearchThreads) void multinomial_search_kernel(
             for (int k = 0; k < kSlots; ++k) {
                 if (__ballot(on[k]) == 0) continue;  // wave-uniform
                 const bool coop = on[k] && vec && len[k] == 16;
-                const int cnt = vec ? line_count_coop(C, x[k], gbase[k], coop) : 0;
+                const int cnt = vec ? line_count_coop(C, x[k], gbase[k], coop,
+                                                      sh_xw + kWave * wave_id(),
+                                                      sh_gw + kWave * wave_id())
+                                    : 0;
                 if (on[k])
                     j[k] = coop ? gbase[k] + cnt
                                 : gbase[k] + first_above(C + gbase[k], len[k], x[k]);
@@ -557,6 +597,7 @@ __global__ __launch_bounds__(kSearchThreads) void multinomial_search_kernel(
 // draws at a time. At these sizes the four dependent launches of the general
 // path cost more than the whole resampling.
 constexpr int64_t kSmallMultiTiles = 2;  // one block runs the tiles one after another
+static_assert(kSmallMultiTiles * kTile >= 16, "the search's line count may read C[0..15]");
 constexpr int kSmallDraws = 8;           // draws per thread per pass
 
 __global__ __launch_bounds__(kTileThreads) void multinomial_small_kernel(
