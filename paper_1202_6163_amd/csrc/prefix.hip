@@ -91,7 +91,9 @@ int launch_table(int64_t P, uint64_t seed, uint32_t instance, char *w, int32_t *
             parts = (n + kTileThreads - 1) / kTileThreads;
             parts = parts > kTableParts ? kTableParts : parts;
         }
-        const int64_t slice = (n + parts - 1) / parts + 2;  // a block's counts (one extra)
+        // a block's counts (one extra); only stratified and systematic count
+        const bool counts = KIND == kStratified || KIND == kSystematic;
+        const int64_t slice = counts ? (n + parts - 1) / parts + 2 : 0;
         const size_t smem = (size_t)n * sizeof(double) + (size_t)slice * sizeof(int32_t);
         if (allow_dynamic_lds(reinterpret_cast<const void *>(&table_kernel<KIND, true>), smem))
             return -3;
@@ -443,6 +445,9 @@ __device__ __forceinline__ int line_count_coop(const double *C, double x, int64_
     return cnt;
 }
 
+// WIDE: groups of more than one line (sub_stride(P) > 16, beyond 2^20
+// particles); the one-line form carries no line-end step.
+template <bool WIDE>
 __global__ __launch_bounds__(kSearchThreads) void multinomial_search_kernel(
     const double *__restrict__ C, int32_t *__restrict__ anc, int64_t P, uint64_t seed,
     uint32_t instance, char *ws_raw, Rows rows)
@@ -509,7 +514,7 @@ __global__ __launch_bounds__(kSearchThreads) void multinomial_search_kernel(
         sh_count[0] = 0;
         sh_count[1] = 0;
     }
-    const bool vec = S == 16 && (((uintptr_t)C) & 15) == 0;
+    const bool vec = (((uintptr_t)C) & 15) == 0;  // S is a power of two >= 16
     __syncthreads();
     const Buckets bk = make_buckets(plo, phi, groups);
     const int lane = lane_id();
@@ -564,6 +569,32 @@ __global__ __launch_bounds__(kSearchThreads) void multinomial_search_kernel(
                 const int g = glo + first_above_lds(sh_sub + glo, ghi - glo + 1, x[k]);
                 gbase[k] = start + (int64_t)g * S;
                 len[k] = min(S, end - gbase[k]);
+            }
+            // Groups wider than one 128-byte line (S > 16, beyond 2^20
+            // particles): narrow each draw to the line holding its ancestor,
+            // the first line whose last C' exceeds x, by bisecting the line
+            // ends (the group's last line ends at the group's end, above x,
+            // and is never read). The slots step together, so their loads
+            // overlap.
+            if (WIDE) {
+                int64_t lbase[kSlots];
+#pragma unroll
+                for (int k = 0; k < kSlots; ++k) lbase[k] = 0;
+                for (int64_t span = S / 16; span > 1;) {
+                    const int64_t half = span >> 1;
+#pragma unroll
+                    for (int k = 0; k < kSlots; ++k) {
+                        const int64_t q = lbase[k] + half - 1;  // the line end probed
+                        const int64_t e = gbase[k] + 16 * q + 15;
+                        if (16 * q + 16 < len[k] && C[e] <= x[k]) lbase[k] += half;
+                    }
+                    span -= half;
+                }
+#pragma unroll
+                for (int k = 0; k < kSlots; ++k) {
+                    gbase[k] += 16 * lbase[k];
+                    len[k] = min((int64_t)16, len[k] - 16 * lbase[k]);
+                }
             }
 #pragma unroll
             for (int k = 0; k < kSlots; ++k) {
@@ -710,15 +741,23 @@ int launch_prefix(int kind, const float *lw, int32_t *anc, int32_t *off, int64_t
                                C, w, seed, instance, status);
         }
         const size_t smem = (size_t)sub_per_part(P) * sizeof(double);
-        if (allow_dynamic_lds(reinterpret_cast<const void *>(&multinomial_search_kernel), smem))
-            return -3;
+        const bool wide = sub_stride(P) > 16;
+        const void *search = wide ? reinterpret_cast<const void *>(&multinomial_search_kernel<true>)
+                                  : reinterpret_cast<const void *>(&multinomial_search_kernel<false>);
+        if (allow_dynamic_lds(search, smem)) return -3;
         // K blocks per part: one per CU of an XCD at most, and 16384 draws
         // each at least (a block's range is then one chunk up to 2^20)
         int64_t K = (P + 16383) / 16384;
         K = K < 1 ? 1 : (K > 32 ? 32 : K);
         const int64_t grid = kParts * K;
-        hipLaunchKernelGGL(multinomial_search_kernel, dim3((uint32_t)grid), dim3(kSearchThreads),
-                           smem, stream, C, anc, P, seed, instance, w, rows);
+        if (wide)
+            hipLaunchKernelGGL(multinomial_search_kernel<true>, dim3((uint32_t)grid),
+                               dim3(kSearchThreads), smem, stream, C, anc, P, seed, instance, w,
+                               rows);
+        else
+            hipLaunchKernelGGL(multinomial_search_kernel<false>, dim3((uint32_t)grid),
+                               dim3(kSearchThreads), smem, stream, C, anc, P, seed, instance, w,
+                               rows);
         break;
     }
     default:

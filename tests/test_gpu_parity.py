@@ -296,10 +296,12 @@ def test_multinomial_heavy_particle_guide(rs):
     assert np.count_nonzero(anc_g == 123457) > P // 2
 
 
-@pytest.mark.parametrize("P", [(1 << 20) + 1, 3_000_001])
+@pytest.mark.parametrize("P", [(1 << 20) + 1, 3_000_001, 1 << 24])
 def test_multinomial_beyond_one_line_groups(rs, P):
-    # above 2^20 particles a group holds more than 16 C' (one 128-byte line),
-    # so the group is searched per lane instead of by eight lanes together
+    # above 2^20 particles a group holds more than 16 C' (one 128-byte line):
+    # each draw first bisects its group's line ends (2, 4 and 16 lines here),
+    # then counts within one line; 2^24 also runs the boundary table at its
+    # largest LDS size (16384 tiles)
     seed, inst = 8, 5
     lw = workloads.normal_logweights(P, 2.0, seed)
     say("multinomial P =", P)
@@ -395,6 +397,24 @@ def test_prefix_deterministic_and_instances_differ(rs):
         assert np.array_equal(a, b)
         c = host(fn(lw, 5, 2))
         assert not np.array_equal(a, c)
+
+
+def test_boundary_only_tables_at_16384_tiles(rs):
+    # 2^24 particles: the table launch's largest LDS case for the kinds that
+    # need only the boundaries (log-sum-exp, adaptive B)
+    P = 1 << 24
+    lw = workloads.normal_logweights(P, 1.0, 5)
+    say("log-sum-exp and adaptive B at P =", P)
+    C, m, _ = oracle.cumulative(lw)
+    ref = m + np.log(C[-1])
+    got = float(host(rs.rs_log_sum_exp(dev(lw)))[0])
+    assert abs(got - ref) <= 1e-12 * max(1.0, abs(ref))
+    B_ref = min(oracle.metropolis_B(P, 1.0 / C[-1], 0.01), 4)
+    B_used = torch.zeros(1, dtype=torch.int32, device="cuda")
+    anc = host(rs.resample_metropolis_adaptive(dev(lw), 3, 1, eps=0.01, B_max=4, B_used=B_used))
+    assert int(host(B_used)[0]) == B_ref
+    ref_anc, _ = oracle.metropolis(lw, B_ref, 3, 1)
+    assert np.array_equal(anc, ref_anc)
 
 
 def test_log_sum_exp(rs):
