@@ -252,6 +252,7 @@ struct TableSums {
 };
 
 constexpr int kRegTiles = 4;
+constexpr int kRunBatch = 8;  // a thread's run is read this many entries at a time
 
 __device__ inline TableSums boundaries(const WsView &ws, int64_t P, double *bound)
 {
@@ -261,9 +262,13 @@ __device__ inline TableSums boundaries(const WsView &ws, int64_t P, double *boun
     __shared__ double sh_W;
     const int64_t n = num_tiles(P);
     const int tid = threadIdx.x;
-    const int64_t per = (n + kTileThreads - 1) / kTileThreads;
-    const int64_t t0 = min(n, (int64_t)tid * per), t1 = min(n, t0 + per);
+    int64_t per = (n + kTileThreads - 1) / kTileThreads;
     const bool reg = per <= kRegTiles;  // uniform
+    // Longer runs get an odd length, so that the 64 runs of a wave start in
+    // different LDS banks (an even length in doubles puts every lane's k-th
+    // element in the same bank).
+    if (!reg) per |= 1;
+    const int64_t t0 = min(n, (int64_t)tid * per), t1 = min(n, t0 + per);
     int fl = 0;
     float m = -INFINITY;
     float mt[kRegTiles];
@@ -293,26 +298,14 @@ __device__ inline TableSums boundaries(const WsView &ws, int64_t P, double *boun
 #pragma unroll
         for (int k = 0; k < kRegTiles; ++k) m = fmaxf(m, mt[k]);
     } else {
-        // longer runs: four tiles' loads in flight at a time
-        for (int64_t c = t0; c < t1; c += kRegTiles) {
-            float mc[kRegTiles];
-            double Sc[kRegTiles];
-            int fc[kRegTiles];
-#pragma unroll
-            for (int k = 0; k < kRegTiles; ++k) {
-                const bool in = c + k < t1;
-                mc[k] = in ? ws.tile_max[c + k] : -INFINITY;
-                Sc[k] = in ? ws.tile_sum[c + k] : 0.0;
-                fc[k] = in ? ws.tile_flags[c + k] : 0;
-            }
-#pragma unroll
-            for (int k = 0; k < kRegTiles; ++k) {
-                if (c + k < t1) {
-                    fl |= fc[k];
-                    m = fmaxf(m, mc[k]);
-                    bound[c + k] = Sc[k];
-                }
-            }
+        // longer runs: the element-wise passes go block-strided (coalesced
+        // loads, many independent ones in flight); only the sums below follow
+        // each thread's contiguous run
+#pragma unroll 8
+        for (int64_t t = tid; t < n; t += kTileThreads) {
+            fl |= ws.tile_flags[t];
+            m = fmaxf(m, ws.tile_max[t]);
+            bound[t] = ws.tile_sum[t];
         }
     }
     // flags and max in one barrier (redi/redf are next written after later barriers)
@@ -342,23 +335,19 @@ __device__ inline TableSums boundaries(const WsView &ws, int64_t P, double *boun
             }
         }
     } else {
-        for (int64_t c = t0; c < t1; c += kRegTiles) {
-            float mc[kRegTiles];
-            double Sc[kRegTiles];
+#pragma unroll 8
+        for (int64_t t = tid; t < n; t += kTileThreads) {
+            const float mc = ws.tile_max[t];
+            bound[t] = (mc > -INFINITY) ? bound[t] * exp((double)mc - (double)m) : 0.0;
+        }
+        __syncthreads();  // the runs below cross the strided ownership (reg is uniform)
+        for (int64_t c = t0; c < t1; c += kRunBatch) {
+            double v[kRunBatch];
 #pragma unroll
-            for (int k = 0; k < kRegTiles; ++k) {
-                const bool in = c + k < t1;
-                mc[k] = in ? ws.tile_max[c + k] : -INFINITY;
-                Sc[k] = in ? bound[c + k] : 0.0;
-            }
+            for (int k = 0; k < kRunBatch; ++k) v[k] = c + k < t1 ? bound[c + k] : 0.0;
 #pragma unroll
-            for (int k = 0; k < kRegTiles; ++k) {
-                if (c + k < t1) {
-                    const double St = (mc[k] > -INFINITY) ? Sc[k] * exp((double)mc[k] - (double)m) : 0.0;
-                    bound[c + k] = St;
-                    local += St;
-                }
-            }
+            for (int k = 0; k < kRunBatch; ++k)
+                if (c + k < t1) local += v[k];  // in tile order
         }
     }
     double run = block_exclusive_sum(local, redd);
@@ -373,10 +362,18 @@ __device__ inline TableSums boundaries(const WsView &ws, int64_t P, double *boun
             }
         }
     } else {
-        for (int64_t t = t0; t < t1; ++t) {
-            run += bound[t];
-            bound[t] = run;
-            tmax = run;
+        for (int64_t c = t0; c < t1; c += kRunBatch) {
+            double v[kRunBatch];
+#pragma unroll
+            for (int k = 0; k < kRunBatch; ++k) v[k] = c + k < t1 ? bound[c + k] : 0.0;
+#pragma unroll
+            for (int k = 0; k < kRunBatch; ++k) {
+                if (c + k < t1) {
+                    run += v[k];
+                    bound[c + k] = run;
+                    tmax = run;
+                }
+            }
         }
     }
     const double carry = block_exclusive_max(tmax, redd);
@@ -391,10 +388,19 @@ __device__ inline TableSums boundaries(const WsView &ws, int64_t P, double *boun
             }
         }
     } else {
-        for (int64_t t = t0; t < t1; ++t) {
-            const double b = fmax(bound[t], carry);
-            bound[t] = b;
-            if (t == n - 1) sh_W = b;
+        for (int64_t c = t0; c < t1; c += kRunBatch) {
+            double v[kRunBatch];
+#pragma unroll
+            for (int k = 0; k < kRunBatch; ++k) v[k] = c + k < t1 ? bound[c + k] : 0.0;
+#pragma unroll
+            for (int k = 0; k < kRunBatch; ++k) {
+                const int64_t t = c + k;
+                if (t < t1) {
+                    const double b = fmax(v[k], carry);
+                    bound[t] = b;
+                    if (t == n - 1) sh_W = b;
+                }
+            }
         }
     }
     __syncthreads();
