@@ -87,7 +87,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU sharding is "
-                                   "design-only (see DESIGN.md)", "n_gpus": args.gpus}))
+                                   "a design only, not built", "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
 
