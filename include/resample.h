@@ -243,7 +243,9 @@ int rs_workspace_log_sum_exp(const void *ws, int64_t P, double *out, hipStream_t
  * observes for small resamplings (Sec. 3). Every instance's ancestors and
  * copied rows are bit-identical to the corresponding single call
  * (resample_metropolis / resample_stratified / resample_systematic, then
- * permute_copy) with the same seed and instance.
+ * permute_copy) with the same seed and instance; an RS_METROPOLIS_ADAPTIVE
+ * instance equals resample_metropolis_adaptive (B from eq. (5) for its own
+ * weights, capped by its B) followed by permute_copy.
  *
  * Usage: fill rs_instance[n] on the host; size the device plan and workspace
  * with rs_batch_plan_bytes / rs_batch_workspace_bytes; rs_batch_plan_init
@@ -260,10 +262,13 @@ typedef struct rs_instance {
     int32_t *status;    /* [device] int32[1] flags of this instance, nullable */
     int64_t P;          /* 0 <= P <= 2^31 - 1 */
     int32_t D;          /* state width when x_in != NULL (>= 1) */
-    int32_t kind;       /* RS_METROPOLIS, RS_STRATIFIED or RS_SYSTEMATIC */
-    uint32_t B;         /* Metropolis iterations */
+    int32_t kind;       /* RS_METROPOLIS, RS_METROPOLIS_ADAPTIVE, RS_STRATIFIED or
+                           RS_SYSTEMATIC */
+    uint32_t B;         /* Metropolis iterations; for RS_METROPOLIS_ADAPTIVE the cap
+                           B_max of eq. (5)'s count (as resample_metropolis_adaptive) */
     uint32_t instance;  /* Philox instance word */
     uint64_t seed;      /* Philox key */
+    double eps;         /* RS_METROPOLIS_ADAPTIVE: eq. (5)'s tolerance (> 0); else unused */
 } rs_instance;
 
 typedef struct rs_batch_tuning {
@@ -326,6 +331,14 @@ int resample_batch_at(const rs_batch_plan *plan, uint32_t instance_add, hipStrea
  *   acc [device] double[n_instances]. Graph-capturable.
  */
 int rs_batch_log_mean_weight(const rs_batch_plan *plan, double *acc, hipStream_t stream);
+/*
+ * out[k] = the Metropolis iterations instance k ran in the plan's last run
+ * (Sec. 2: the B of eq. (5) an RS_METROPOLIS_ADAPTIVE instance computed from
+ * its weights, capped by its B; the fixed B of an RS_METROPOLIS instance; 0
+ * for the prefix resamplers and empty instances).
+ *   out [device] uint32[n_instances]. Stream-ordered after that run.
+ */
+int rs_batch_iterations(const rs_batch_plan *plan, uint32_t *out, hipStream_t stream);
 
 /*
  * Bootstrap particle filter around the resampler (Sec. 1: initialisation,
@@ -357,6 +370,16 @@ int filter_propagate_weight_batch(const float *x_in, float *x_out, float *lw, in
 int filter_propagate_weight(const float *x_in, float *x_out, float *lw, int64_t P, int32_t D,
                             const double *A, const float *y, double q, double r, uint64_t seed,
                             uint32_t t, hipStream_t stream);
+/*
+ * The filter's log-likelihood estimate (Sec. 1: the weights' sum at each
+ * step, the normalising constant of the weighting step, estimates the
+ * observation density): out = sum_t (lse_t - log P), added in time order,
+ * where lse_t = log sum_i exp(lw_i) of step t (rs_workspace_log_sum_exp or
+ * rs_log_sum_exp). A NaN or -inf factor propagates.
+ *   lse [device] double[T], T >= 0; out [device] double[1] (output); P >= 1
+ * Errors: RS_EINVAL (null pointers, T < 0, P out of range, out inside lse).
+ */
+int filter_loglik(const double *lse, int32_t T, int64_t P, double *out, hipStream_t stream);
 
 /*
  * Number of Metropolis iterations B (Sec. 2, eqs. (1)-(5)) for P particles

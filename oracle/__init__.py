@@ -278,6 +278,56 @@ def metropolis_B(P, w_max, eps):
     return int(_lib.oracle_metropolis_B(int(P), float(w_max), float(eps)))
 
 
+# ---------------------------------------------------------------- all-core build
+_omp = None
+
+
+def _omp_lib():
+    """liboracle_omp.so: the same source built with OpenMP (CPU baseline)."""
+    global _omp
+    if _omp is None:
+        path = _build.LIB_OMP
+        src = os.path.join(_HERE, "resample_oracle.c")
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(src):
+            _build.build(openmp=True)
+        lib = ctypes.CDLL(path)
+        P = ctypes.POINTER
+        lib.oracle_metropolis.restype = ctypes.c_int
+        lib.oracle_metropolis.argtypes = [P(ctypes.c_float), P(ctypes.c_int32), ctypes.c_int64,
+                                          ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32,
+                                          P(ctypes.c_int32)]
+        lib.oracle_permute_copy.restype = ctypes.c_int
+        lib.oracle_permute_copy.argtypes = [P(ctypes.c_int32), P(ctypes.c_float),
+                                            P(ctypes.c_float), ctypes.c_int64, ctypes.c_int32]
+        _omp = lib
+    return _omp
+
+
+def metropolis_all_cores(lw, B, seed, instance=0):
+    """oracle.metropolis on every core (OpenMP over the chains; same bits)."""
+    lw = _f32(lw)
+    anc = np.empty(lw.size, dtype=np.int32)
+    st = np.zeros(1, dtype=np.int32)
+    _check(_omp_lib().oracle_metropolis(_ptr(lw, ctypes.c_float), _ptr(anc, ctypes.c_int32),
+                                        lw.size, int(B), int(seed), int(instance),
+                                        _ptr(st, ctypes.c_int32)), "metropolis_all_cores")
+    return anc, int(st[0])
+
+
+def permute_copy_all_cores(anc, x_in):
+    """oracle.permute_copy on every core (OpenMP over the rows; same bits)."""
+    anc = _i32(anc)
+    x_in = _f32(x_in)
+    P = anc.size
+    D = x_in.size // P
+    out = np.zeros_like(x_in)
+    rc = _check(_omp_lib().oracle_permute_copy(_ptr(anc, ctypes.c_int32),
+                                               _ptr(x_in, ctypes.c_float),
+                                               _ptr(out, ctypes.c_float), P, D),
+                "permute_copy_all_cores")
+    return out, rc
+
+
 def resampling_error(off, lw):
     off = _i32(off)
     lw = _f32(lw)

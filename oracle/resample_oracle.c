@@ -8,6 +8,12 @@
  * the benchmark's CPU-baseline leg may load it; the HIP library never includes,
  * links or calls it, and it shares no source with the HIP library.
  *
+ * The same source is also built a second time with OpenMP (liboracle_omp.so)
+ * for the all-core CPU baseline: only the particle loops of the Metropolis
+ * resampler and of the state copy carry a pragma, each iteration is
+ * independent (counter-based random numbers, disjoint output rows), so that
+ * build returns the same bits; the single-threaded build ignores the pragmas.
+ *
  * Arithmetic rules: IEEE-754 binary32 / binary64 with round-to-nearest-even,
  * built with -O2 -ffp-contract=off -fno-fast-math on SSE2 (no x87 excess
  * precision), so every expression below rounds exactly where it is written.
@@ -180,6 +186,8 @@ int oracle_metropolis(const float *lw, int32_t *anc, int64_t P, uint32_t B, uint
 {
     if (!lw || !anc || P < 1 || P > INT32_MAX) return ORACLE_EINVAL;
     int32_t flags = screen_weights(lw, P) & (ORACLE_FLAG_NAN | ORACLE_FLAG_POSINF);
+    /* chains are independent: the OpenMP build (CPU baseline only) splits them */
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < P; ++i) anc[i] = metropolis_chain(lw, P, B, seed, instance, i);
     if (status) *status |= flags;
     return 0;
@@ -371,6 +379,7 @@ int oracle_ancestors_to_offspring(const int32_t *anc, int32_t *off, int64_t P)
     if (!anc || !off || P < 1) return ORACLE_EINVAL;
     for (int64_t j = 0; j < P; ++j) off[j] = 0;
     int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
     for (int64_t i = 0; i < P; ++i) {
         if (anc[i] < 0 || anc[i] >= P) { bad = 1; continue; }
         off[anc[i]] += 1;
@@ -395,6 +404,7 @@ int oracle_permute_copy(const int32_t *anc, const float *x_in, float *x_out, int
 {
     if (!anc || !x_in || !x_out || P < 1 || D < 1) return ORACLE_EINVAL;
     int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
     for (int64_t i = 0; i < P; ++i) {
         if (anc[i] < 0 || anc[i] >= P) { bad = 1; continue; }
         memcpy(x_out + i * (int64_t)D, x_in + (int64_t)anc[i] * D, (size_t)D * sizeof(float));

@@ -31,7 +31,8 @@ class Instance(ctypes.Structure):
                 ("x_in", ctypes.c_void_p),
                 ("x_out", ctypes.c_void_p), ("status", ctypes.c_void_p), ("P", ctypes.c_int64),
                 ("D", ctypes.c_int32), ("kind", ctypes.c_int32), ("B", ctypes.c_uint32),
-                ("instance", ctypes.c_uint32), ("seed", ctypes.c_uint64)]
+                ("instance", ctypes.c_uint32), ("seed", ctypes.c_uint64),
+                ("eps", ctypes.c_double)]
 
 
 class BatchTuning(ctypes.Structure):
@@ -90,12 +91,14 @@ def _load():
         "rs_probe_gather": (ctypes.c_int, [vp, i64, i64, i64, u32, vp, vp]),
         "rs_probe_philox": (ctypes.c_int, [u64, i64, i64, vp, vp]),
         "filter_init": (ctypes.c_int, [vp, i64, ctypes.c_int32, u64, vp]),
+        "filter_loglik": (ctypes.c_int, [vp, ctypes.c_int32, i64, vp, vp]),
         "filter_init_batch": (ctypes.c_int, [vp, ctypes.c_int32, i64, ctypes.c_int32, u64, vp]),
         "filter_propagate_weight_batch": (ctypes.c_int, [vp, vp, vp, ctypes.c_int32, i64,
                                                          ctypes.c_int32, vp, vp, vp,
                                                          ctypes.c_double, u64, u32, vp]),
         "resample_batch_at": (ctypes.c_int, [ctypes.POINTER(BatchPlan), u32, vp]),
         "rs_batch_log_mean_weight": (ctypes.c_int, [ctypes.POINTER(BatchPlan), vp, vp]),
+        "rs_batch_iterations": (ctypes.c_int, [ctypes.POINTER(BatchPlan), vp, vp]),
         "filter_propagate_weight": (ctypes.c_int, [vp, vp, vp, i64, ctypes.c_int32, vp, vp,
                                                    ctypes.c_double, ctypes.c_double, u64, u32,
                                                    vp]),

@@ -14,8 +14,9 @@ import torch
 from . import _lib
 from ._lib import check, lib
 
-STRATIFIED, SYSTEMATIC, MULTINOMIAL, METROPOLIS, LOG_SUM_EXP = (
-    _lib.STRATIFIED, _lib.SYSTEMATIC, _lib.MULTINOMIAL, _lib.METROPOLIS, _lib.LOG_SUM_EXP)
+STRATIFIED, SYSTEMATIC, MULTINOMIAL, METROPOLIS, LOG_SUM_EXP, METROPOLIS_ADAPTIVE = (
+    _lib.STRATIFIED, _lib.SYSTEMATIC, _lib.MULTINOMIAL, _lib.METROPOLIS, _lib.LOG_SUM_EXP,
+    _lib.METROPOLIS_ADAPTIVE)
 FLAG_NAN, FLAG_POSINF, FLAG_ALL_NEGINF, FLAG_BAD_ANCESTOR, FLAG_INTERNAL = (
     _lib.FLAG_NAN, _lib.FLAG_POSINF, _lib.FLAG_ALL_NEGINF, _lib.FLAG_BAD_ANCESTOR,
     _lib.FLAG_INTERNAL)
@@ -96,7 +97,12 @@ def resample_metropolis_adaptive(lw, seed, instance=0, eps=0.01, B_max=8192, anc
     anc = torch.empty(P, dtype=torch.int32, device=lw.device) if anc is None else anc
     _need(anc, torch.int32, "anc", P)
     if B_used is not None:
-        _need(B_used, torch.int32, "B_used", 1)
+        # the C ABI writes a uint32; int32 storage reads the same (B_max < 2^31)
+        if B_used.dtype not in (torch.int32, torch.uint32):
+            raise TypeError(f"B_used: expected a uint32 (or int32) tensor, got {B_used.dtype}")
+        _need(B_used, B_used.dtype, "B_used", 1)
+        if int(B_max) >= 1 << 31:
+            raise ValueError("B_max must be below 2^31")
     if ws is None:
         ws = workspace(P, _lib.METROPOLIS_ADAPTIVE, lw.device, stream)
     check(lib.resample_metropolis_adaptive(_ptr(lw), _ptr(anc), P, float(eps), int(B_max),
@@ -352,6 +358,16 @@ def filter_propagate_weight_batch(x_in, A, y_t, q, r, seed, t, K, x_out, lw, str
                                             int(t), _stream_handle(stream)),
           "filter_propagate_weight_batch")
     return x_out, lw
+
+
+def filter_loglik(lse, P, out=None, stream=None):
+    """sum_t (lse[t] - log P) on the device (float64 tensor of one element)."""
+    _need(lse, torch.float64, "lse")
+    out = torch.empty(1, dtype=torch.float64, device=lse.device) if out is None else out
+    _need(out, torch.float64, "out", 1)
+    check(lib.filter_loglik(_ptr(lse), int(lse.numel()), int(P), _ptr(out),
+                            _stream_handle(stream)), "filter_loglik")
+    return out
 
 
 def filter_propagate_weight(x_in, A, y_t, q, r, seed, t, x_out=None, lw=None, stream=None):

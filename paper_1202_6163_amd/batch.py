@@ -11,9 +11,10 @@ import torch
 
 from . import _lib
 from ._lib import check, lib
-from .api import METROPOLIS, STRATIFIED, SYSTEMATIC, _need, _stream_handle
+from .api import METROPOLIS, METROPOLIS_ADAPTIVE, STRATIFIED, SYSTEMATIC, _need, _stream_handle
 
-KINDS = {"metropolis": METROPOLIS, "stratified": STRATIFIED, "systematic": SYSTEMATIC}
+KINDS = {"metropolis": METROPOLIS, "metropolis_adaptive": METROPOLIS_ADAPTIVE,
+         "stratified": STRATIFIED, "systematic": SYSTEMATIC}
 DEFAULT_TUNING = dict(chains_per_item=1024, unroll=8, lds_max_p=8192, blocks=0)
 
 
@@ -28,9 +29,11 @@ def default_tuning():
 
 class Batch:
     def __init__(self, instances, tuning=None, device=None, stream=None, async_upload=False):
-        """instances: dicts with lw, anc, kind ('metropolis' | 'stratified' |
-        'systematic'), seed, instance, and optionally B, x_in, x_out, status,
-        off (offspring output of a stratified/systematic instance).
+        """instances: dicts with lw, anc, kind ('metropolis' |
+        'metropolis_adaptive' | 'stratified' | 'systematic'), seed, instance,
+        and optionally B (for 'metropolis_adaptive' the cap of eq. (5)'s
+        count), eps (eq. (5)'s tolerance), x_in, x_out, status, off (offspring
+        output of a stratified/systematic instance).
         With async_upload the plan goes through pinned host memory held by
         this object and the call does not wait for the device."""
         self.device = torch.device(device) if device is not None else torch.device(
@@ -62,7 +65,7 @@ class Batch:
                                    x_out.data_ptr() if x_out is not None else None,
                                    st.data_ptr() if st is not None else None, lw.numel(), D,
                                    KINDS[d["kind"]], int(d.get("B", 0)), int(d["instance"]),
-                                   int(d["seed"]))
+                                   int(d["seed"]), float(d.get("eps", 0.0)))
         self._arr = arr
         t = dict(default_tuning(), **(tuning or {}))
         self.tuning = _lib.BatchTuning(t["chains_per_item"], t["unroll"], t["lds_max_p"],
@@ -101,6 +104,15 @@ class Batch:
         check(lib.rs_batch_log_mean_weight(ctypes.byref(self.plan),
                                            ctypes.c_void_p(acc.data_ptr()),
                                            _stream_handle(stream)), "rs_batch_log_mean_weight")
+
+    def iterations(self, out, stream=None):
+        """out[k] = the Metropolis iterations instance k ran in the last run
+        (eq. (5)'s count for 'metropolis_adaptive'); 4-byte integer device tensor."""
+        if out.element_size() != 4 or out.numel() != self.plan.n_instances or not out.is_cuda:
+            raise ValueError("out must be a 4-byte integer device tensor, one entry per instance")
+        check(lib.rs_batch_iterations(ctypes.byref(self.plan), ctypes.c_void_p(out.data_ptr()),
+                                      _stream_handle(stream)), "rs_batch_iterations")
+        return out
 
     @property
     def particles(self):

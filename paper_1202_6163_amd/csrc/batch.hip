@@ -3,8 +3,10 @@
 // motivates the Metropolis resampler by exactly this repeated use) in one
 // graph replay of three persistent launches.
 //
-//   launch 1  tile reductions of every stratified/systematic instance
-//   launch 2  the per-instance tables (one block each)
+//   launch 1  tile reductions of every stratified/systematic (and adaptive
+//             Metropolis) instance
+//   launch 2  the per-instance tables (one block each; an adaptive
+//             Metropolis table computes eq. (5)'s B)
 //   launch 3  Metropolis chains and stratified/systematic fills of every
 //             instance, each item followed by the ancestor-indexed copy of
 //             its rows (fused: the ancestors are still in LDS)
@@ -61,8 +63,11 @@ __global__ __launch_bounds__(kThreads) void batch_table_kernel(const BatchInstan
         const uint32_t inst = I.instance + instance_add;
         if (I.kind == kStratified)
             table_body<kStratified>(I.P, I.seed, inst, I.ws, I.status, nullptr, bound, count);
-        else
+        else if (I.kind == kSystematic)
             table_body<kSystematic>(I.P, I.seed, inst, I.ws, I.status, nullptr, bound, count);
+        else  // adaptive Metropolis: eq. (5)'s B (capped by I.B) into the header
+            table_body<kAdaptiveB>(I.P, I.seed, inst, I.ws, I.status, nullptr, bound, count,
+                                   I.eps, I.B, nullptr);
     }
 }
 
@@ -70,7 +75,7 @@ __global__ __launch_bounds__(kThreads) void batch_table_kernel(const BatchInstan
 // copy of their rows. sh_anc holds the item's ancestors for the copy; w is
 // LDS-staged weights or the instance's lw.
 template <int UNROLL>
-__device__ void metropolis_item(const BatchInstance &I, uint32_t inst, int64_t first,
+__device__ void metropolis_item(const BatchInstance &I, uint32_t B, uint32_t inst, int64_t first,
                                 int64_t count, float *staged, int32_t *sh_anc)
 {
     const uint32_t P = (uint32_t)I.P;
@@ -84,7 +89,7 @@ __device__ void metropolis_item(const BatchInstance &I, uint32_t inst, int64_t f
     for (int64_t r = threadIdx.x; r < count; r += kThreads) {
         const uint32_t i = (uint32_t)(first + r);
         fl |= mh::weight_flags(w[i]);
-        const int32_t a = (int32_t)mh::chain<UNROLL>(w, P, I.B, I.seed, inst, i);
+        const int32_t a = (int32_t)mh::chain<UNROLL>(w, P, B, I.seed, inst, i);
         I.anc[i] = a;
         if (I.x_in) sh_anc[r] = a;
     }
@@ -113,11 +118,13 @@ __global__ __launch_bounds__(kThreads) void batch_main_kernel(const BatchInstanc
         const int2 item = items[it];
         const BatchInstance &I = insts[item.x];
         const uint32_t inst = I.instance + instance_add;
-        if (I.kind == kMetropolisKind) {
+        if (I.kind == kMetropolisKind || I.kind == kAdaptiveKind) {
             const int64_t first = (int64_t)item.y * chains_per_item;
             const int64_t count = min((int64_t)chains_per_item, I.P - first);
-            metropolis_item<UNROLL>(I, inst, first, count, I.P <= lds_max_p ? staging : nullptr,
-                                    sh_anc);
+            // an adaptive instance reads the B its table left in the header
+            const uint32_t B = I.kind == kAdaptiveKind ? ws_view(I.ws, I.P).h->B : I.B;
+            metropolis_item<UNROLL>(I, B, inst, first, count,
+                                    I.P <= lds_max_p ? staging : nullptr, sh_anc);
         } else if (I.kind == kStratified) {
             fill_body<kStratified, false>(I.lw, I.anc, I.off, I.P, I.seed, inst, nullptr, I.ws,
                                           item.y, I.x_in, I.x_out, I.D, I.status, Cs, sh_anc,
@@ -134,7 +141,7 @@ uint32_t grid_of(int32_t items, int32_t blocks) { return (uint32_t)max(1, min(it
 
 // acc[k] += log of instance k's mean weight, lse_k - log P_k (the likelihood
 // factor of Sec. 1's weighting step), from the header its table left; NaN
-// for instances without a table (Metropolis, P = 0).
+// for instances without a table (fixed-B Metropolis, P = 0).
 __global__ __launch_bounds__(kThreads) void batch_log_mean_weight_kernel(const BatchInstance *insts,
                                                                          int32_t n, double *acc)
 {
@@ -145,7 +152,31 @@ __global__ __launch_bounds__(kThreads) void batch_log_mean_weight_kernel(const B
     }
 }
 
+// out[k] = the Metropolis iterations instance k ran in the plan's last run:
+// eq. (5)'s count from its table for an adaptive instance, its B for a
+// fixed one, 0 for other kinds and empty instances.
+__global__ __launch_bounds__(kThreads) void batch_iterations_kernel(const BatchInstance *insts,
+                                                                    int32_t n, uint32_t *out)
+{
+    for (int32_t k = blockIdx.x * kThreads + threadIdx.x; k < n; k += gridDim.x * kThreads) {
+        const BatchInstance &I = insts[k];
+        uint32_t B = 0;
+        if (I.P > 0 && I.kind == kMetropolisKind) B = I.B;
+        if (I.P > 0 && I.kind == kAdaptiveKind && I.ws) B = ws_view(I.ws, I.P).h->B;
+        out[k] = B;
+    }
+}
+
 }  // namespace
+
+int launch_batch_iterations(const BatchInstance *insts, int32_t n, uint32_t *out,
+                            hipStream_t stream)
+{
+    const uint32_t grid = (uint32_t)max(1, min((n + kThreads - 1) / kThreads, 1024));
+    hipLaunchKernelGGL(batch_iterations_kernel, dim3(grid), dim3(kThreads), 0, stream, insts, n,
+                       out);
+    return launch_status();
+}
 
 int launch_batch(const BatchLaunch &L, hipStream_t stream)
 {

@@ -41,12 +41,13 @@ bool valid_instance(const rs_instance &d)
 {
     if (d.P < 0 || d.P > kMaxP) return false;
     if (d.P == 0) return true;
-    if (d.kind != RS_METROPOLIS && d.kind != RS_STRATIFIED && d.kind != RS_SYSTEMATIC)
-        return false;
+    const bool metro = d.kind == RS_METROPOLIS || d.kind == RS_METROPOLIS_ADAPTIVE;
+    if (!metro && d.kind != RS_STRATIFIED && d.kind != RS_SYSTEMATIC) return false;
+    if (d.kind == RS_METROPOLIS_ADAPTIVE && !(d.eps > 0.0)) return false;
     // Metropolis writes ancestors; stratified/systematic ancestors and/or offspring; the
     // state copy reads the ancestors
-    if (!d.lw || (d.kind == RS_METROPOLIS && !d.anc) || (!d.anc && !d.off)) return false;
-    if (d.off && d.kind == RS_METROPOLIS) return false;
+    if (!d.lw || (metro && !d.anc) || (!d.anc && !d.off)) return false;
+    if (d.off && metro) return false;
     if (d.x_in && !d.anc) return false;
     const size_t p = (size_t)d.P;
     if (d.anc && overlaps(d.lw, 4 * p, d.anc, 4 * p)) return false;
@@ -64,6 +65,10 @@ bool valid_instance(const rs_instance &d)
 
 bool is_prefix(const rs_instance &d) { return d.kind == RS_STRATIFIED || d.kind == RS_SYSTEMATIC; }
 
+// Instances with a tile reduction and a table: the prefix resamplers, and
+// adaptive Metropolis (its table leaves eq. (5)'s B in the workspace header).
+bool has_table(const rs_instance &d) { return is_prefix(d) || d.kind == RS_METROPOLIS_ADAPTIVE; }
+
 struct Layout {
     int32_t n_tile = 0, n_table = 0, n_main = 0;
     int64_t max_tiles = 0;
@@ -76,12 +81,14 @@ bool layout_of(const rs_instance *d, int32_t n, const rs_batch_tuning &t, Layout
     for (int32_t k = 0; k < n; ++k) {
         if (!valid_instance(d[k])) return false;
         if (d[k].P == 0) continue;
-        if (is_prefix(d[k])) {
+        if (has_table(d[k])) {
             const int64_t nt = rs::num_tiles(d[k].P);
             tiles += nt;
             tables += 1;
-            mains += rs::num_fill_blocks(d[k].P);
             L->max_tiles = std::max(L->max_tiles, nt);
+        }
+        if (is_prefix(d[k])) {
+            mains += rs::num_fill_blocks(d[k].P);
         } else {
             mains += (d[k].P + t.chains_per_item - 1) / t.chains_per_item;
         }
@@ -114,7 +121,7 @@ size_t rs_batch_workspace_bytes(const rs_instance *descs, int32_t n)
     if (!descs || n < 1) return 0;
     size_t total = 0;
     for (int32_t k = 0; k < n; ++k)
-        if (descs[k].P > 0 && is_prefix(descs[k]))
+        if (descs[k].P > 0 && has_table(descs[k]))
             total += al(rs_workspace_bytes(descs[k].P, descs[k].kind));
     return total;
 }
@@ -167,13 +174,16 @@ int rs_batch_plan_init(rs_batch_plan *plan, const rs_instance *descs, int32_t n,
         I.instance = d.instance;
         I.D = d.x_in ? d.D : 0;
         I.kind = d.kind;
+        I.eps = d.kind == RS_METROPOLIS_ADAPTIVE ? d.eps : 0.0;
         if (d.P == 0) continue;
-        if (is_prefix(d)) {
+        const int64_t tiles = rs::num_tiles(d.P);
+        if (has_table(d)) {
             I.ws = static_cast<char *>(ws) + ws_off;
             ws_off += al(rs_workspace_bytes(d.P, d.kind));
-            const int64_t tiles = rs::num_tiles(d.P);
             for (int64_t q = 0; q < tiles; ++q) tile_items[nt++] = make_int2(k, (int)q);
             table_items[nb++] = k;
+        }
+        if (is_prefix(d)) {
             const int64_t fills = rs::num_fill_blocks(d.P);
             for (int64_t g = 0; g < fills; ++g)
                 mains.push_back({make_int2(k, (int)g), g < tiles ? 4096.0 : 64.0});
@@ -233,6 +243,14 @@ int rs_batch_log_mean_weight(const rs_batch_plan *plan, double *acc, hipStream_t
     if (!plan || !plan->dev || plan->n_instances < 1 || !acc) return RS_EINVAL;
     const rs::BatchInstance *insts = static_cast<const rs::BatchInstance *>(plan->dev);
     const int rc = rs::launch_batch_log_mean_weight(insts, plan->n_instances, acc, stream);
+    return rc == 0 ? RS_OK : RS_EHIP;
+}
+
+int rs_batch_iterations(const rs_batch_plan *plan, uint32_t *out, hipStream_t stream)
+{
+    if (!plan || !plan->dev || plan->n_instances < 1 || !out) return RS_EINVAL;
+    const rs::BatchInstance *insts = static_cast<const rs::BatchInstance *>(plan->dev);
+    const int rc = rs::launch_batch_iterations(insts, plan->n_instances, out, stream);
     return rc == 0 ? RS_OK : RS_EHIP;
 }
 

@@ -313,6 +313,13 @@ int resample_metropolis_adaptive(const float *lw, int32_t *anc, int64_t P, doubl
                                                  B_used, status, t, stream));
 }
 
+int filter_loglik(const double *lse, int32_t T, int64_t P, double *out, hipStream_t stream)
+{
+    if (!lse || !out || T < 0 || P < 1 || P > kMaxP) return RS_EINVAL;
+    if (overlaps(lse, 8 * (size_t)T, out, 8)) return RS_EINVAL;
+    return map_rc(rs::launch_filter_loglik(lse, T, P, out, stream));
+}
+
 int filter_init(float *x, int64_t P, int32_t D, uint64_t seed, hipStream_t stream)
 {
     if (P == 0) return RS_OK;

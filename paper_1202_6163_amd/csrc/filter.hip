@@ -148,7 +148,25 @@ uint32_t filter_grid(int64_t P)
     return (uint32_t)g;
 }
 
+// log Z-hat = sum_t (lse_t - log P), added term by term in time order (the
+// order a sequential filter accumulates it in). One lane: T is small.
+__global__ void filter_loglik_kernel(const double *__restrict__ lse, int32_t T, int64_t P,
+                                     double *__restrict__ out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double log_p = log((double)P);
+    double ll = 0.0;
+    for (int32_t t = 0; t < T; ++t) ll += lse[t] - log_p;
+    out[0] = ll;
+}
+
 }  // namespace
+
+int launch_filter_loglik(const double *lse, int32_t T, int64_t P, double *out, hipStream_t stream)
+{
+    hipLaunchKernelGGL(filter_loglik_kernel, dim3(1), dim3(64), 0, stream, lse, T, P, out);
+    return launch_status();
+}
 
 int launch_filter_init(float *x, int64_t P, int64_t K, int32_t D, uint64_t seed,
                        hipStream_t stream)

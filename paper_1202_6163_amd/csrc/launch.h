@@ -89,6 +89,7 @@ int launch_philox_probe(uint64_t seed, uint32_t threads, uint32_t rounds, uint32
 
 // ---------------------------------------------------------------- batches
 constexpr int kMetropolisKind = 3;  // RS_METROPOLIS
+constexpr int kAdaptiveKind = 5;    // RS_METROPOLIS_ADAPTIVE (B from eq. (5) on the device)
 
 // One instance of a batch as the kernels read it (device memory).
 struct BatchInstance {
@@ -98,13 +99,15 @@ struct BatchInstance {
     const float *x_in;  // nullptr: no copy
     float *x_out;
     int32_t *status;
-    char *ws;           // this instance's prefix workspace (stratified/systematic)
+    char *ws;           // this instance's prefix workspace (stratified/systematic,
+                        // and the table of an adaptive Metropolis instance)
     int64_t P;
     uint64_t seed;
-    uint32_t B;
+    uint32_t B;         // iterations; the cap of eq. (5)'s count for kAdaptiveKind
     uint32_t instance;
     int32_t D;
     int32_t kind;
+    double eps;         // eq. (5)'s tolerance (kAdaptiveKind)
 };
 
 struct BatchLaunch {
@@ -120,11 +123,14 @@ struct BatchLaunch {
 };
 
 int launch_batch(const BatchLaunch &launch, hipStream_t stream);
+int launch_batch_iterations(const BatchInstance *insts, int32_t n, uint32_t *out,
+                            hipStream_t stream);
 int launch_batch_log_mean_weight(const BatchInstance *insts, int32_t n, double *acc,
                                  hipStream_t stream);
 
 // K filters of P particles each (K = 1: one filter); q_k: per-filter
 // variances (device) or nullptr for the shared q.
+int launch_filter_loglik(const double *lse, int32_t T, int64_t P, double *out, hipStream_t stream);
 int launch_filter_init(float *x, int64_t P, int64_t K, int32_t D, uint64_t seed,
                        hipStream_t stream);
 

@@ -9,8 +9,6 @@ from the reduction the resampler performs anyway (a separate log-sum-exp
 only for the fixed-B Metropolis resampler, which never sums the weights).
 The whole run can be captured once into a HIP graph and replayed.
 """
-import math
-
 import torch
 
 from . import api
@@ -85,8 +83,8 @@ class BootstrapFilter:
         return g
 
     def loglik(self, lse):
-        T = lse.numel()
+        """sum_t (lse_t - log P), summed on the device by the library."""
         flags = int(self.status.item())
         if flags:
             raise RuntimeError(f"resampling flagged the weights (status {flags})")
-        return float(lse.sum().item()) - T * math.log(self.P)
+        return float(api.filter_loglik(lse, self.P).item())

@@ -2,11 +2,19 @@
 
 Requests (log-weights of P particles, a resampler, optional D-float state
 rows) arrive over time. The scheduler admits a request when its device
-footprint fits the HBM budget, keeps its weights and state resident on the
-device, and at every turn packs the admitted requests that are not yet running
-into one batch (the library's batched launch) on a free stream, so batches
-overlap on the device while new requests keep arriving. A finished batch
-releases its requests' memory, admitting the next ones.
+footprint fits the HBM budget, uploads its weights and state from host memory
+and keeps them resident on the device, and at every turn packs the admitted
+requests that are not yet running into one batch (the library's batched
+launch) on a free stream, so batches overlap on the device while new requests
+keep arriving. A finished batch releases its requests' memory, admitting the
+next ones. Metropolis requests take B from eq. (5) for their own weights
+(computed on the device, capped), so the chains are converged whenever the
+cap allows; the record counts the requests whose cap bound.
+
+Latency is measured on one host clock: arrival, admission and start are
+stamped when the server acts, completion when the server's poll first sees
+the request's event done (so it includes the upload and any wait for a
+stream, and overstates the device's completion by at most one poll).
 
 The scheduling policy (Scheduler) is pure host logic over an executor
 interface, so it is tested on the CPU with a fake executor and clock; the
@@ -29,9 +37,11 @@ class Request:
     P: int
     kind: str
     D: int = 0
-    B: int = 64
+    B: int = 64        # Metropolis: the cap of eq. (5)'s iteration count
     seed: int = 0
     sigma: float = 1.0
+    slot: int = 0      # which client payload holds the request's data
+    eps: float = 0.01  # eq. (5)'s tolerance
     # filled in by the scheduler
     t_admit: float = math.nan
     t_start: float = math.nan
@@ -42,12 +52,13 @@ class Request:
 
 def footprint(req):
     """Device bytes a request holds while resident: log-weights, ancestors,
-    state in and out, a prefix workspace and its share of the batch plan."""
+    state in and out, its workspace as the library sizes it (tile partials
+    and table: every kind served here has one, Metropolis for eq. (5)'s B)
+    and its share of the batch plan."""
+    from ._lib import METROPOLIS_ADAPTIVE, STRATIFIED, lib
     P, D = req.P, req.D
-    ws = 0
-    if req.kind in ("stratified", "systematic"):
-        tiles = (P + 1023) // 1024
-        ws = 2048 + tiles * 40 + 256 * 8
+    kind = METROPOLIS_ADAPTIVE if req.kind == "metropolis" else STRATIFIED
+    ws = lib.rs_workspace_bytes(P, kind) + 256
     return 8 * P + 8 * P * D + ws + PLAN_BYTES_PER_REQUEST
 
 
@@ -118,6 +129,7 @@ class Scheduler:
             for r in batch:
                 r.t_start = now
                 r.batch = self.n_batches
+                r.state["batch_size"] = len(batch)
             self.running[s] = (self.ex.submit(s, batch), batch)
             self.n_batches += 1
             started += 1
@@ -127,47 +139,84 @@ class Scheduler:
         return not (self.waiting or self.ready or self.running)
 
 
-class GpuExecutor:
-    """Runs batches on n_streams HIP streams with the library's batched launch;
-    completion times come from HIP events on the device clock."""
+class Payloads:
+    """The clients' side of the request data: a few payload slots in pinned
+    host memory, each holding log-weights lw = sigma_k * z of P_MAX particles
+    and P_MAX x 16 state values. A request names its slot; its weights are the
+    first P of the slot's and its state rows the first P * D of the slot's
+    values. The server uploads them at admission."""
 
-    def __init__(self, n_streams=4, tuning=None, keep_results=False, max_single_p=1 << 20):
+    def __init__(self, p_max=1 << 20, n_slots=None, pin=True):
         import torch
 
-        from . import api, workloads
-        self.torch, self.workloads, self.api = torch, workloads, api
+        from . import workloads
+        self.p_max = int(p_max)
+        self.n_slots = int(n_slots or workloads.SERVE_SLOTS)
+        self.lw, self.x = [], []
+        for k in range(self.n_slots):
+            lw, x = workloads.serve_payload(k, self.p_max)
+            t_lw, t_x = torch.from_numpy(lw), torch.from_numpy(x)
+            self.lw.append(t_lw.pin_memory() if pin else t_lw)
+            self.x.append(t_x.pin_memory() if pin else t_x)
+
+    def host(self, req):
+        """(lw[P], x[P, D] or None): host views of a request's data."""
+        lw = self.lw[req.slot][:req.P]
+        x = self.x[req.slot][:req.P * req.D].view(req.P, req.D) if req.D else None
+        return lw, x
+
+
+class GpuExecutor:
+    """Runs batches on n_streams HIP streams with the library's batched launch.
+
+    A batch of one request goes through the single-call entry points (the
+    same results as the batched launch, without building a plan); with
+    max_batch = 1 at the scheduler every request gets its own launches."""
+
+    def __init__(self, n_streams=4, tuning=None, keep_results=False, max_single_p=1 << 20,
+                 payloads=None):
+        """keep_results: True, or a set of request ids whose outputs are
+        copied to the host at release (for checking)."""
+        import torch
+
+        from . import api
+        self.torch, self.api = torch, api
         self.dev = torch.device("cuda", torch.cuda.current_device())
         self.streams = [torch.cuda.Stream(self.dev) for _ in range(n_streams)]
         self.n_streams = n_streams
         self.tuning = tuning
         self.keep_results = keep_results
-        # A batch of one request goes through the single-call entry points
-        # (the same results as the batched launch, without building a plan);
-        # each stream keeps a prefix workspace for up to max_single_p particles.
+        self.payloads = payloads if payloads is not None else Payloads(max_single_p)
+        # each stream keeps a workspace for single requests up to max_single_p particles
         self.max_single_p = int(max_single_p)
         self.single_ws = [api.workspace(self.max_single_p, api.STRATIFIED, self.dev, stream=st)
                           for st in self.streams]
-        self.t0_event = torch.cuda.Event(enable_timing=True)
-        self.t0_event.record()
+        self.upload = torch.cuda.Stream(self.dev)
         torch.cuda.synchronize()
         self.t0_host = time.perf_counter()
-        self.upload = torch.cuda.Stream(self.dev)
 
     def now(self):
         return time.perf_counter() - self.t0_host
 
     def admit(self, req):
-        """Make the request resident: its weights and state rows are created on
-        the device (seeded), as a filter running there would hold them."""
+        """Make the request resident: upload its weights and state rows from
+        the client's pinned host memory (asynchronously, on the upload
+        stream; the request's batch waits for that copy)."""
         torch = self.torch
         st = req.state
+        lw_h, x_h = self.payloads.host(req)
         with torch.cuda.stream(self.upload):
-            st["lw"] = device_logweights(req.P, req.sigma, req.seed, self.dev)
+            st["lw"] = torch.empty(req.P, dtype=torch.float32, device=self.dev)
+            st["lw"].copy_(lw_h, non_blocking=True)
             st["anc"] = torch.empty(req.P, dtype=torch.int32, device=self.dev)
             st["status"] = torch.zeros(1, dtype=torch.int32, device=self.dev)
             if req.D:
-                st["x_in"] = device_state_rows(req.P, req.D, self.dev)
+                st["x_in"] = torch.empty((req.P, req.D), dtype=torch.float32, device=self.dev)
+                st["x_in"].copy_(x_h, non_blocking=True)
                 st["x_out"] = torch.empty((req.P, req.D), dtype=torch.float32, device=self.dev)
+            if req.kind == "metropolis":
+                st["B_used"] = torch.zeros(1, dtype=torch.int32, device=self.dev)
+                st["B_host"] = torch.zeros(1, dtype=torch.int32, pin_memory=True)
             st["ready"] = torch.cuda.Event()
             st["ready"].record(self.upload)
 
@@ -181,7 +230,8 @@ class GpuExecutor:
         for r in reqs:
             st = r.state
             stream.wait_event(st["ready"])
-            d = dict(lw=st["lw"], anc=st["anc"], kind=r.kind, B=r.B, seed=r.seed,
+            kind = "metropolis_adaptive" if r.kind == "metropolis" else r.kind
+            d = dict(lw=st["lw"], anc=st["anc"], kind=kind, B=r.B, eps=r.eps, seed=r.seed,
                      instance=r.id & 0xFFFFFFFF, status=st["status"])
             if r.D:
                 d["x_in"], d["x_out"] = st["x_in"], st["x_out"]
@@ -189,9 +239,16 @@ class GpuExecutor:
         with torch.cuda.stream(stream):
             b = Batch(insts, tuning=self.tuning, stream=stream, async_upload=True)
             b.run(stream=stream)
-            ev = torch.cuda.Event(enable_timing=True)
+            # eq. (5)'s B each Metropolis request used, to pinned host memory
+            # before the completion event (read at release without a sync)
+            B_all = b.iterations(torch.empty(len(reqs), dtype=torch.int32, device=self.dev),
+                                 stream=stream)
+            for k, r in enumerate(reqs):
+                if r.kind == "metropolis":
+                    r.state["B_host"].copy_(B_all[k:k + 1], non_blocking=True)
+            ev = torch.cuda.Event()
             ev.record(stream)
-        return (b, ev)
+        return [b, ev, None]
 
     def _submit_single(self, s, r):
         torch, api = self.torch, self.api
@@ -201,49 +258,41 @@ class GpuExecutor:
         inst = r.id & 0xFFFFFFFF
         with torch.cuda.stream(stream):
             if r.kind == "metropolis":
-                api.resample_metropolis(st["lw"], r.B, r.seed, inst, anc=st["anc"],
-                                        status=st["status"])
+                api.resample_metropolis_adaptive(st["lw"], r.seed, inst, eps=r.eps, B_max=r.B,
+                                                 anc=st["anc"], B_used=st["B_used"],
+                                                 ws=self.single_ws[s], status=st["status"])
             else:
                 fn = api.resample_stratified if r.kind == "stratified" else api.resample_systematic
                 fn(st["lw"], r.seed, inst, anc=st["anc"], ws=self.single_ws[s],
                    status=st["status"])
             if r.D:
                 api.permute_copy(st["anc"], st["x_in"], x_out=st["x_out"], status=st["status"])
-            ev = torch.cuda.Event(enable_timing=True)
+            if r.kind == "metropolis":
+                st["B_host"].copy_(st["B_used"], non_blocking=True)
+            ev = torch.cuda.Event()
             ev.record(stream)
-        return (None, ev)
+        return [None, ev, None]
 
     def poll(self, handle):
-        return handle[1].query()
+        if handle[2] is None and handle[1].query():
+            handle[2] = self.now()  # the server sees the batch done
+        return handle[2] is not None
 
     def finished_time(self, handle):
-        return self.t0_event.elapsed_time(handle[1]) * 1e-3
+        return handle[2]
 
     def release(self, req):
         st = req.state
-        if self.keep_results:
+        if req.kind == "metropolis":
+            st["B_used_host"] = int(st["B_host"][0])  # copied before the completion event
+        keep = self.keep_results
+        if keep is True or (keep and req.id in keep):
             st["anc_host"] = st["anc"].cpu()
             if req.D:
                 st["x_out_host"] = st["x_out"].cpu()
             st["status_host"] = int(st["status"].item())
-        for k in ("lw", "anc", "x_in", "x_out", "status", "ready"):
+        for k in ("lw", "anc", "x_in", "x_out", "status", "ready", "B_used", "B_host"):
             st.pop(k, None)
-
-
-def device_logweights(P, sigma, seed, device):
-    """Seeded N(0, sigma^2) log-weights drawn on the device (request payload)."""
-    import torch
-    g = torch.Generator(device=device)
-    g.manual_seed(int(seed))
-    return torch.randn(int(P), generator=g, device=device, dtype=torch.float32) * float(sigma)
-
-
-def device_state_rows(P, D, device):
-    """State rows X[i, d] = i + d / 8 built on the device."""
-    import torch
-    i = torch.arange(int(P), device=device, dtype=torch.float64)[:, None]
-    d = torch.arange(int(D), device=device, dtype=torch.float64)[None, :]
-    return (i + d / 8.0).to(torch.float32).contiguous()
 
 
 def serve(requests, executor, budget_bytes, max_batch=256, time_limit=None):
@@ -273,9 +322,14 @@ def summarize(sched, duration):
     admit = np.array([r.t_admit - r.t_arrival for r in done])
     parts = sum(r.P for r in done)
     span = max(r.t_done for r in done) - min(r.t_arrival for r in done)
+    sizes = np.array([r.state.get("batch_size", 1) for r in done])
+    metro = [r for r in done if r.kind == "metropolis"]
+    B_used = np.array([r.state["B_used_host"] for r in metro if "B_used_host" in r.state])
     return {
         "requests": len(done), "rejected": len(sched.rejected), "batches": sched.n_batches,
         "mean_batch": len(done) / max(sched.n_batches, 1),
+        "requests_in_batches_of_2_or_more": float(np.mean(sizes >= 2)),
+        "admission_waits": int(np.count_nonzero(admit > 1e-4)),
         "p50_latency_ms": float(np.percentile(lat, 50) * 1e3),
         "p99_latency_ms": float(np.percentile(lat, 99) * 1e3),
         "max_latency_ms": float(lat.max() * 1e3),
@@ -285,14 +339,19 @@ def summarize(sched, duration):
         "particles_per_s": parts / span if span > 0 else float("nan"),
         "offered_particles_per_s": parts / duration if duration else float("nan"),
         "peak_resident_bytes": sched.peak_used,
+        "metropolis_requests": len(metro),
+        "metropolis_B_median": float(np.median(B_used)) if B_used.size else None,
+        "metropolis_B_capped": int(np.count_nonzero(B_used >= np.array(
+            [r.B for r in metro if "B_used_host" in r.state]))) if B_used.size else 0,
     }
 
 
-def make_requests(rate=2000.0, duration=60.0, seed=0, p_lo=10, p_hi=20, B=64):
+def make_requests(rate=2000.0, duration=60.0, seed=0, p_lo=10, p_hi=20, B=1024, eps=0.01):
+    """The request stream; B is the cap of a Metropolis request's eq. (5) count."""
     from . import workloads
     out = []
     for d in workloads.request_stream(rate=rate, duration=duration, seed=seed, p_lo=p_lo,
                                       p_hi=p_hi, B=B):
         out.append(Request(id=d["id"], t_arrival=d["t"], P=d["P"], kind=d["kind"], D=d["D"],
-                           B=d["B"], seed=d["seed"], sigma=d["sigma"]))
+                           B=d["B"], seed=d["seed"], sigma=d["sigma"], slot=d["slot"], eps=eps))
     return out

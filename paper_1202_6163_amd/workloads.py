@@ -105,9 +105,39 @@ def batch_logweights(P, sig, seed=0):
 
 
 # ----------------------------------------------------------------- serving
-def request_stream(rate=2000.0, duration=60.0, seed=0, p_lo=10, p_hi=20, s_lo=0.5, s_hi=4.0,
-                   dims=(1, 16), B=64):
-    """Poisson arrivals: list of dicts (t_arrival s, P, sigma, D, kind, B, seed)."""
+SERVE_SLOTS = 16      # client payload slots
+SERVE_SIGMA = (0.5, 4.0)
+
+
+def serve_slot_sigma(k, n_slots=SERVE_SLOTS, s_lo=SERVE_SIGMA[0], s_hi=SERVE_SIGMA[1]):
+    """The weight spread of payload slot k: the slots cover [s_lo, s_hi] evenly."""
+    return s_lo + (s_hi - s_lo) * (k + 0.5) / n_slots
+
+
+def serve_payload(k, p_max=1 << 20):
+    """Payload slot k: (lw[p_max] = sigma_k z, x[p_max * 16] standard normal)."""
+    rng = np.random.default_rng(7000 + k)
+    z = rng.standard_normal(int(p_max), dtype=np.float32)
+    lw = (np.float32(serve_slot_sigma(k)) * z).astype(np.float32)
+    x = rng.standard_normal(int(p_max) * 16, dtype=np.float32)
+    return lw, x
+
+
+# Requests with weights this even use the Metropolis resampler; the rest
+# stratified or systematic. Sec. 3 finds Metropolis competitive only when the
+# weights vary little: above this spread eq. (5)'s B at 2^20 particles
+# exceeds a thousand iterations (sigma = 1: B = 257), where the prefix-sum
+# resamplers are faster.
+SERVE_METROPOLIS_MAX_SIGMA = 1.1
+
+
+def request_stream(rate=2000.0, duration=60.0, seed=0, p_lo=10, p_hi=20, dims=(1, 16), B=64,
+                   n_slots=SERVE_SLOTS):
+    """Poisson arrivals: list of dicts (t_arrival s, P, sigma, slot, D, kind, B, seed).
+    A request's data lives in payload slot `slot` (uniform over the slots), so
+    its sigma is that slot's: uniform over SERVE_SIGMA in n_slots steps. The
+    client picks the resampler from its weights' spread: Metropolis up to
+    SERVE_METROPOLIS_MAX_SIGMA, otherwise stratified or systematic."""
     rng = np.random.default_rng(seed)
     n_max = int(rate * duration * 1.2 + 100)
     gaps = rng.exponential(1.0 / rate, size=n_max)
@@ -115,8 +145,11 @@ def request_stream(rate=2000.0, duration=60.0, seed=0, p_lo=10, p_hi=20, s_lo=0.
     n = int(np.searchsorted(t, duration))
     t = t[:n]
     P = np.floor(np.exp2(p_lo + (p_hi - p_lo) * rng.random(n))).astype(np.int64)
-    sig = rng.uniform(s_lo, s_hi, size=n)
+    slot = rng.integers(0, n_slots, size=n)
     D = rng.choice(np.asarray(dims), size=n)
-    kind = rng.choice(np.asarray(["metropolis", "stratified"]), size=n)
-    return [dict(id=k, t=float(t[k]), P=int(P[k]), sigma=float(sig[k]), D=int(D[k]),
-                 kind=str(kind[k]), B=int(B), seed=int(k)) for k in range(n)]
+    prefix = rng.choice(np.asarray(["stratified", "systematic"]), size=n)
+    sig = [serve_slot_sigma(int(slot[k]), n_slots) for k in range(n)]
+    kind = ["metropolis" if sig[k] <= SERVE_METROPOLIS_MAX_SIGMA else str(prefix[k])
+            for k in range(n)]
+    return [dict(id=k, t=float(t[k]), P=int(P[k]), sigma=sig[k], slot=int(slot[k]), D=int(D[k]),
+                 kind=kind[k], B=int(B), seed=int(k)) for k in range(n)]

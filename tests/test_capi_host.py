@@ -189,6 +189,10 @@ def test_filter_argument_errors(L):
     f = ctypes.c_void_p
     assert lib.filter_init(None, 10, 8, 1, None) == L.RS_EINVAL
     assert lib.filter_init(f(0x1000), 10, 65, 1, None) == L.RS_EINVAL
+    assert lib.filter_loglik(None, 10, 8, f(0x1000), None) == L.RS_EINVAL
+    assert lib.filter_loglik(f(0x1000), -1, 8, f(0x9000), None) == L.RS_EINVAL
+    assert lib.filter_loglik(f(0x1000), 10, 0, f(0x9000), None) == L.RS_EINVAL
+    assert lib.filter_loglik(f(0x1000), 10, 8, f(0x1008), None) == L.RS_EINVAL  # out inside lse
     assert lib.filter_propagate_weight(f(0x1000), f(0x1000), f(0x90000), 10, 4, f(0x80000),
                                        f(0x70000), 0.1, 0.5, 1, 1, None) == L.RS_EINVAL
     assert lib.filter_propagate_weight(f(0x1000), f(0x20000), f(0x90000), 10, 4, f(0x80000),
@@ -301,3 +305,4 @@ def test_batched_filter_and_batch_step_arguments(L):
     assert lib.rs_batch_log_mean_weight(None, f(0x1000), None) == L.RS_EINVAL
     plan = L.BatchPlan()
     assert lib.rs_batch_log_mean_weight(ctypes.byref(plan), f(0x1000), None) == L.RS_EINVAL
+

@@ -9,6 +9,7 @@ import torch
 
 import oracle
 from paper_1202_6163_amd import workloads
+from parity import explained_mismatches
 
 pytestmark = pytest.mark.gpu
 
@@ -23,7 +24,7 @@ def rs():
 def make_instances(n, p_lo, p_hi, D, seed, with_copy=True):
     P, sig = workloads.batch_instances(n, seed=seed, p_lo=p_lo, p_hi=p_hi)
     rng = np.random.default_rng(seed + 7)
-    kinds = rng.choice(["metropolis", "stratified", "systematic"], size=n)
+    kinds = rng.choice(["metropolis", "metropolis_adaptive", "stratified", "systematic"], size=n)
     insts = []
     for k in range(n):
         Pk = int(P[k])
@@ -33,7 +34,9 @@ def make_instances(n, p_lo, p_hi, D, seed, with_copy=True):
         d = dict(lw=lw, anc=torch.full((Pk,), -7, dtype=torch.int32, device="cuda"),
                  kind=str(kinds[k]), B=int(rng.integers(1, 80)), seed=1000 + k,
                  instance=k, status=torch.zeros(1, dtype=torch.int32, device="cuda"))
-        if d["kind"] != "metropolis" and k % 2 == 0:
+        if d["kind"] == "metropolis_adaptive":  # B caps eq. (5)'s count, which some reach
+            d["B"], d["eps"] = int(rng.integers(1, 300)), float(rng.choice([0.01, 0.1]))
+        if not d["kind"].startswith("metropolis") and k % 2 == 0:
             d["off"] = torch.full((Pk,), -7, dtype=torch.int32, device="cuda")
         if with_copy and k % 5 != 1:
             Dk = D if k % 3 else 3  # some rows of a width the vector path cannot take
@@ -48,6 +51,9 @@ def single(rs, d):
     off = None
     if d["kind"] == "metropolis":
         anc = rs.resample_metropolis(lw, d["B"], d["seed"], d["instance"])
+    elif d["kind"] == "metropolis_adaptive":
+        anc = rs.resample_metropolis_adaptive(lw, d["seed"], d["instance"], eps=d["eps"],
+                                              B_max=d["B"])
     else:
         off = torch.empty_like(d["anc"]) if "off" in d else None
         anc = getattr(rs, f"resample_{d['kind']}")(lw, d["seed"], d["instance"], off=off)
@@ -93,9 +99,38 @@ def test_batch_matches_oracle_sample(rs):
         if d["kind"] == "metropolis":
             ref, _ = oracle.metropolis(lw, d["B"], d["seed"], d["instance"])
             assert np.array_equal(d["anc"].cpu().numpy(), ref)
+        elif d["kind"] == "metropolis_adaptive":
+            C, _, _ = oracle.cumulative(lw)
+            B = min(oracle.metropolis_B(lw.size, 1.0 / C[-1], d["eps"]), d["B"])
+            ref, _ = oracle.metropolis(lw, B, d["seed"], d["instance"])
+            assert np.array_equal(d["anc"].cpu().numpy(), ref)
         else:
-            ref, _ = getattr(oracle, d["kind"])(lw, d["seed"], d["instance"])
-            assert np.count_nonzero(d["anc"].cpu().numpy() != ref) <= 2
+            ref, _, C = getattr(oracle, d["kind"])(lw, d["seed"], d["instance"], want_cumw=True)
+            explained_mismatches(d["kind"], d["anc"].cpu().numpy(), ref, C, d["seed"],
+                                 d["instance"])
+
+
+def test_batch_iterations_report_eq5(rs):
+    # the B each instance ran: eq. (5)'s (capped) for adaptive instances, equal
+    # to the single call's B_used and to the oracle's eq. (5)
+    from paper_1202_6163_amd.batch import Batch
+    insts = make_instances(40, 6, 15, 4, seed=5)
+    b = Batch(insts)
+    b.run()
+    got = b.iterations(torch.empty(len(insts), dtype=torch.int32, device="cuda")).cpu().numpy()
+    for k, d in enumerate(insts):
+        P = d["lw"].numel()
+        if P == 0 or not d["kind"].startswith("metropolis"):
+            assert got[k] == 0, k
+        elif d["kind"] == "metropolis":
+            assert got[k] == d["B"], k
+        else:
+            Bu = torch.zeros(1, dtype=torch.int32, device="cuda")
+            rs.resample_metropolis_adaptive(d["lw"], d["seed"], d["instance"], eps=d["eps"],
+                                            B_max=d["B"], B_used=Bu)
+            C, _, _ = oracle.cumulative(d["lw"].cpu().numpy())
+            want = min(oracle.metropolis_B(P, 1.0 / C[-1], d["eps"]), d["B"])
+            assert got[k] == int(Bu.item()) == want, (k, got[k], want)
 
 
 def test_batch_full_workload_and_graph_replays(rs):
