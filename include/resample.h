@@ -154,6 +154,34 @@ int resample_multinomial(const float *lw, int32_t *anc, int64_t P, uint64_t seed
                          int32_t *status, hipStream_t stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * stratified, systematic or multinomial resampler (kind RS_STRATIFIED,
+ * RS_SYSTEMATIC or RS_MULTINOMIAL) exactly as resample_stratified /
+ * resample_systematic / resample_multinomial compute it (the same kernels,
+ * the same results), with no workspace argument: the workspace is a
+ * library-owned device array of RS_STATIC_SCRATCH_BYTES per GPU, reserved
+ * when the library is loaded on that GPU and held until the process ends.
+ * The call allocates nothing (no hipMalloc or hipFree, here or in any
+ * library routine it calls).
+ *   lw, anc, off, cumw, status  as for resample_stratified (off: stratified
+ *                               and systematic only)
+ * Limits: rs_workspace_bytes(P, kind) <= RS_STATIC_SCRATCH_BYTES, which
+ * holds for every kind up to P = 2^20 (and for stratified/systematic far
+ * beyond); a larger P returns RS_EWORKSPACE before any launch.
+ * Every call on one GPU shares that GPU's array (the last call's contents
+ * stay; no call needs them cleared), so two calls that may overlap on one
+ * GPU (different streams without ordering between them) race and give
+ * unspecified results; order them like calls sharing a workspace.
+ * Errors: RS_EINVAL, RS_EWORKSPACE, RS_EHIP (also if the array's address
+ * cannot be found on the current device).
+ */
+#define RS_STATIC_SCRATCH_BYTES ((size_t)12 << 20)
+int resample_prefix_static(int kind, const float *lw, int32_t *anc, int32_t *off, int64_t P,
+                           uint64_t seed, uint32_t instance, double *cumw, int32_t *status,
+                           hipStream_t stream);
+
+/*
  * One resampling step with the state copy fused into the resampler's own
  * launches: the ancestors (and, for stratified/systematic, the offspring)
  * are exactly those of resample_metropolis / resample_stratified /

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libresample.so")
 HEADER = os.path.join(ROOT, "include", "resample.h")
 
 RS_OK, RS_EINVAL, RS_EWORKSPACE, RS_EHIP = 0, -1, -2, -3
+RS_STATIC_SCRATCH_BYTES = 12 << 20  # the no-allocation entry point's array (resample.h)
 FLAG_NAN, FLAG_POSINF, FLAG_ALL_NEGINF, FLAG_BAD_ANCESTOR, FLAG_INTERNAL = 1, 2, 4, 8, 16
 STRATIFIED, SYSTEMATIC, MULTINOMIAL, METROPOLIS, LOG_SUM_EXP, METROPOLIS_ADAPTIVE = 0, 1, 2, 3, 4, 5
 
@@ -78,6 +79,8 @@ def _load():
                                                         u32, vp, sz, vp, i32p, vp]),
         "resample_systematic": (ctypes.c_int, [vp, vp, vp, i64, u64, u32, vp, vp, sz, i32p, vp]),
         "resample_multinomial": (ctypes.c_int, [vp, vp, i64, u64, u32, vp, vp, sz, i32p, vp]),
+        "resample_prefix_static": (ctypes.c_int, [ctypes.c_int, vp, vp, vp, i64, u64, u32, vp,
+                                                  i32p, vp]),
         "ancestors_to_offspring": (ctypes.c_int, [vp, vp, i64, i32p, vp]),
         "resample_and_copy": (ctypes.c_int, [ctypes.c_int, vp, vp, vp, i64, u32, u64, u32, vp, vp,
                                              ctypes.c_int32, vp, sz, i32p, vp]),

@@ -189,6 +189,22 @@ int resample_systematic(const float *lw, int32_t *anc, int32_t *off, int64_t P, 
                        stream);
 }
 
+int resample_prefix_static(int kind, const float *lw, int32_t *anc, int32_t *off, int64_t P,
+                           uint64_t seed, uint32_t instance, double *cumw, int32_t *status,
+                           hipStream_t stream)
+{
+    if (kind != RS_STRATIFIED && kind != RS_SYSTEMATIC && kind != RS_MULTINOMIAL)
+        return RS_EINVAL;
+    if (P == 0) return RS_OK;
+    if (P < 0 || P > kMaxP) return RS_EINVAL;
+    if (rs_workspace_bytes(P, kind) > RS_STATIC_SCRATCH_BYTES) return RS_EWORKSPACE;
+    void *ws = nullptr;
+    const int rc = rs::static_scratch(&ws);
+    if (rc) return map_rc(rc);
+    return prefix_call(kind, lw, anc, off, P, seed, instance, cumw, ws, RS_STATIC_SCRATCH_BYTES,
+                       status, stream);
+}
+
 int resample_multinomial(const float *lw, int32_t *anc, int64_t P, uint64_t seed,
                          uint32_t instance, double *cumw, void *ws, size_t ws_bytes,
                          int32_t *status, hipStream_t stream)

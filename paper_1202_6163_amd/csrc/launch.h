@@ -55,6 +55,11 @@ int launch_prefix(int kind, const float *lw, int32_t *anc, int32_t *off, int64_t
                   uint32_t instance, double *cumw, void *ws, int32_t *status,
                   hipStream_t stream, const Rows &rows = Rows());
 
+// Device address of this device's no-allocation workspace (the file-scope
+// array in prefix.hip, RS_STATIC_SCRATCH_BYTES), looked up on first use.
+// Returns 0, -1 (device index out of range) or -3.
+int static_scratch(void **out);
+
 int launch_log_sum_exp(const float *lw, int64_t P, double *out, void *ws, int32_t *status,
                        hipStream_t stream);
 int launch_workspace_lse(const void *ws, int64_t P, double *out, hipStream_t stream);

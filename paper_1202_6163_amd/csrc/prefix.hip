@@ -40,10 +40,13 @@
 // left-to-right sum to a few ulps.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "common.h"
 #include "launch.h"
 #include "prefix.h"
 #include "prefix_impl.h"
+#include "resample.h"
 
 namespace rs {
 namespace {
@@ -769,6 +772,37 @@ int launch_prefix(int kind, const float *lw, int32_t *anc, int32_t *off, int64_t
 __global__ void workspace_lse_kernel(const char *ws_raw, int64_t P, double *out)
 {
     if (threadIdx.x == 0) *out = ws_view(const_cast<char *>(ws_raw), P).h->lse;
+}
+
+// Workspace of the no-allocation entry point (resample_prefix_static): a
+// file-scope device array, one per GPU the library runs on, held until the
+// process ends. In host code `scratch` names a host-side stand-in, not the
+// device memory: its device address comes from hipGetSymbolAddress, looked up
+// once per device (with that device current) and kept here.
+static __device__ __align__(256) char scratch[RS_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void *g_scratch[kMaxDevices] = {};
+}  // namespace
+
+int static_scratch(void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return record_hip_error(e);
+    if (dev < 0 || dev >= kMaxDevices) return -1;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return record_hip_error(e);
+        if (!p) return -3;
+        g_scratch[dev] = p;
+    }
+    *out = g_scratch[dev];
+    return 0;
 }
 
 int launch_workspace_lse(const void *ws, int64_t P, double *out, hipStream_t stream)

@@ -306,3 +306,23 @@ def test_batched_filter_and_batch_step_arguments(L):
     plan = L.BatchPlan()
     assert lib.rs_batch_log_mean_weight(ctypes.byref(plan), f(0x1000), None) == L.RS_EINVAL
 
+
+def test_static_entry_arguments_and_limit(L):
+    # the no-allocation entry point: the header's array size, every kind fits
+    # P = 2^20, and bad arguments or sizes beyond the array are refused
+    # before any launch (and before the array's address is looked up)
+    hdr = open(os.path.join(ROOT, "include", "resample.h")).read()
+    m = re.search(r"#define RS_STATIC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", hdr)
+    assert m and int(m.group(1)) << int(m.group(2)) == L.RS_STATIC_SCRATCH_BYTES
+    lib = L.lib
+    for kind in (L.STRATIFIED, L.SYSTEMATIC, L.MULTINOMIAL):
+        assert lib.rs_workspace_bytes(1 << 20, kind) <= L.RS_STATIC_SCRATCH_BYTES
+    f = ctypes.c_void_p
+    assert lib.resample_prefix_static(7, f(0x1000), f(0x90000), None, 10, 1, 0, None, None,
+                                      None) == L.RS_EINVAL
+    assert lib.resample_prefix_static(0, f(0x1000), f(0x90000), None, -1, 1, 0, None, None,
+                                      None) == L.RS_EINVAL
+    assert lib.resample_prefix_static(2, f(0x1000), f(0x90000000), None, 1 << 22, 1, 0, None,
+                                      None, None) == L.RS_EWORKSPACE
+    assert lib.resample_prefix_static(0, None, f(0x90000), None, 0, 1, 0, None, None,
+                                      None) == L.RS_OK  # empty: nothing to do
