@@ -440,6 +440,31 @@ int rs_metropolis_set_tuning(const rs_metropolis_tuning *t); /* t [host] */
 int rs_metropolis_get_tuning(rs_metropolis_tuning *t);       /* t [host] */
 
 /*
+ * Form of the stratified and systematic single calls (resample_stratified,
+ * resample_systematic, resample_and_copy, resample_prefix_static; the
+ * results are the same bits in every form). Sec. 2 notes that the prefix sum
+ * needs thread communication and several kernel launches, and Sec. 3 that
+ * launch overhead dominated at small sizes; up to P = 2^20 these calls can
+ * run as ONE launch in which the blocks exchange their tile sums through
+ * device memory (tagged words, no fence) instead of through kernel
+ * boundaries.
+ *   path    RS_PATH_AUTO (the faster form as measured on the MI355X: the
+ *           launches at every size so far), RS_PATH_LAUNCHES (always the tile
+ *           reduction, table and fill launches) or RS_PATH_ONEPASS (the one
+ *           launch wherever it applies: P <= 2^20 and the device holds all
+ *           its blocks at once; else the launches)
+ *   wait_ns bound on a one-pass block's wait for the other blocks' tile sums
+ *           before it computes the missing ones itself (< 0: the default,
+ *           100 us; 0: never wait). It changes speed, never results.
+ * Process-wide. Returns RS_OK or RS_EINVAL (unknown path).
+ */
+#define RS_PATH_AUTO 0
+#define RS_PATH_LAUNCHES 1
+#define RS_PATH_ONEPASS 2
+int rs_prefix_set_path(int path, int64_t wait_ns);
+int rs_prefix_get_path(void); /* the current path */
+
+/*
  * Self-check of the Metropolis acceptance test. The kernel decides
  * log u < d from the hardware log2 approximation whenever d is farther than
  * 2^-16 |log u| from it, and from the correctly rounded binary64-based log

@@ -20,6 +20,7 @@ RS_OK, RS_EINVAL, RS_EWORKSPACE, RS_EHIP = 0, -1, -2, -3
 RS_STATIC_SCRATCH_BYTES = 12 << 20  # the no-allocation entry point's array (resample.h)
 FLAG_NAN, FLAG_POSINF, FLAG_ALL_NEGINF, FLAG_BAD_ANCESTOR, FLAG_INTERNAL = 1, 2, 4, 8, 16
 STRATIFIED, SYSTEMATIC, MULTINOMIAL, METROPOLIS, LOG_SUM_EXP, METROPOLIS_ADAPTIVE = 0, 1, 2, 3, 4, 5
+PATH_AUTO, PATH_LAUNCHES, PATH_ONEPASS = 0, 1, 2  # rs_prefix_set_path
 
 
 class Tuning(ctypes.Structure):
@@ -114,6 +115,8 @@ def _load():
                                               vp, sz, vp, vp]),
         "resample_batch": (ctypes.c_int, [ctypes.POINTER(BatchPlan), vp]),
         "rs_metropolis_get_tuning": (ctypes.c_int, [ctypes.POINTER(Tuning)]),
+        "rs_prefix_set_path": (ctypes.c_int, [ctypes.c_int, i64]),
+        "rs_prefix_get_path": (ctypes.c_int, []),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -299,6 +299,19 @@ def rs_metropolis_get_tuning():
                 lanes_per_chain=t.lanes_per_chain)
 
 
+def rs_prefix_set_path(path, wait_ns=-1):
+    """Form of the stratified/systematic single calls: "auto", "launches" or
+    "onepass" (same results; see rs_prefix_set_path in resample.h)."""
+    code = {"auto": _lib.PATH_AUTO, "launches": _lib.PATH_LAUNCHES,
+            "onepass": _lib.PATH_ONEPASS}[path] if isinstance(path, str) else int(path)
+    check(lib.rs_prefix_set_path(code, int(wait_ns)), "rs_prefix_set_path")
+
+
+def rs_prefix_get_path():
+    return {_lib.PATH_AUTO: "auto", _lib.PATH_LAUNCHES: "launches",
+            _lib.PATH_ONEPASS: "onepass"}[int(lib.rs_prefix_get_path())]
+
+
 def _apply_stored_tuning():
     """Launch parameters from the autotuner's table for this device, if any."""
     from . import autotune

@@ -412,6 +412,13 @@ int rs_probe_philox(uint64_t seed, int64_t threads, int64_t rounds, uint32_t *ou
     return map_rc(rs::launch_philox_probe(seed, (uint32_t)threads, (uint32_t)rounds, out, stream));
 }
 
+int rs_prefix_set_path(int path, int64_t wait_ns)
+{
+    return rs::set_prefix_path(path, wait_ns) == 0 ? RS_OK : RS_EINVAL;
+}
+
+int rs_prefix_get_path(void) { return rs::get_prefix_path(); }
+
 int rs_metropolis_set_tuning(const rs_metropolis_tuning *t)
 {
     if (!t) return RS_EINVAL;

@@ -11,6 +11,13 @@
 // cumulative weights) or the cumulative weights (multinomial, searched by a
 // fourth launch). Kernel boundaries order the phases, so no block waits on
 // another and the workspace needs no initialisation.
+//
+// Up to kOnePassMaxTiles tiles the stratified/systematic resampler can also
+// run as one launch (onepass_kernel in prefix.hip): every block publishes its
+// tiles' (max, sum, flags) as tagged 64-bit words in the `pub` section and
+// reads all of them back; the tags come from a call counter in the `epoch`
+// section, so stale or uninitialised words are never taken for current ones
+// and this path, too, needs no initialisation.
 #pragma once
 
 #include <stddef.h>
@@ -41,7 +48,8 @@ struct alignas(64) WsHeader {
 };
 
 struct WsLayout {
-    size_t header, tile_max, tile_sum, tile_flags, bound, count, win, sub, guide, part, cumw, total;
+    size_t header, tile_max, tile_sum, tile_flags, bound, count, win, epoch, pub, sub, guide, part,
+        cumw, total;
 };
 
 __host__ __device__ inline size_t ws_align(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -92,9 +100,12 @@ __host__ __device__ inline WsLayout ws_layout(int64_t P, bool with_cumw)
     L.bound = L.tile_flags + ws_align(n * sizeof(int32_t));
     L.count = L.bound + ws_align(n * sizeof(double));
     L.win = L.count + ws_align(n * sizeof(int32_t));
+    // one-pass path: the call counter, then three tagged words per tile
+    L.epoch = L.win + ws_align((size_t)num_windows(P) * sizeof(int32_t));
+    L.pub = L.epoch + ws_align(sizeof(uint64_t));
     // the multinomial sections (group ends, guide, draw parts, C) sit past the shared
     // ones at the same offsets whatever the kind; only the size differs
-    L.sub = L.win + ws_align((size_t)num_windows(P) * sizeof(int32_t));
+    L.sub = L.pub + ws_align(n * 3 * sizeof(uint64_t));
     L.guide = L.sub + ws_align((size_t)num_sub(P) * sizeof(double));
     L.part = L.guide + ws_align((size_t)(kParts * guide_stride(P)) * sizeof(uint16_t));
     L.cumw = L.part + ws_align((size_t)P + 16);
@@ -115,5 +126,10 @@ __host__ __device__ inline int64_t num_fill_blocks(int64_t P)
 // instances the extra launch costs more than the redundant scan, for large
 // ones (measured at 1024 tiles) the other way round.
 constexpr int64_t kFusedTableTiles = 64;
+
+// The one-pass stratified/systematic launch: at most this many tiles (P <=
+// 2^20), kOnePassTiles tiles per block.
+constexpr int64_t kOnePassMaxTiles = 1024;
+constexpr int kOnePassTiles = 2;
 
 }  // namespace rs

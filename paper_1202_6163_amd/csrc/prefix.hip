@@ -40,6 +40,7 @@
 // left-to-right sum to a few ulps.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <mutex>
 
 #include "common.h"
@@ -145,6 +146,353 @@ int launch_fill(const float *lw, int32_t *anc, int32_t *off, int64_t P, uint64_t
                            instance, cumw, w, status, rows);
     }
     return 0;
+}
+
+// ------------------------------------------------------ one-pass fill
+// Stratified/systematic resampling in one launch (P <= 2^20): the three
+// phases of the launches above (tile reduction, boundaries and counts, fill)
+// with the grid-wide step done inside the kernel. Block b owns tiles b and
+// b + G (G = gridDim.x = ceil(n / 2)). It loads their log-weights (and, with
+// DS > 0, their state rows) once, reduces each tile exactly as
+// tile_reduce_body does and publishes (max, sum, flags) as three 64-bit words
+// per tile, each carrying a 32-bit tag in its high half. The block then reads
+// every tile's words back, runs the same boundaries code as the table launch
+// on them (so every block holds the same bits the three-launch path computes)
+// and fills its own tiles from registers and LDS, plus the overflow windows
+// of heavy tiles it is assigned.
+//
+// No release fence is needed: each word is self-contained, written and read
+// with relaxed device-scope atomics, which go to the point of coherence
+// shared by the eight XCDs (no L2 write-back). A word counts only when its tag
+// equals pub_tag(e, t, k), e being this call's value of the workspace's call
+// counter: words of earlier calls (smaller e) and uninitialised memory fail
+// that test except with probability 2^-32 per word (2^-96 for a tile's three).
+// Every block raises the counter past e once it holds all the values; before
+// that every block has read e (it published after reading it), so the next
+// call, ordered after this one, sees a larger value. The wait is bounded: a
+// block that has not seen a tile's words after wait_ticks of the real-time
+// clock reduces that tile itself (the same function, the same bits), so the
+// results never depend on all blocks being resident at once; only the speed
+// does.
+__device__ __forceinline__ uint32_t pub_tag(uint64_t e, int64_t t, int k)
+{
+    // a 32-bit integer hash (lowbias32 finaliser) of (call, tile, word)
+    uint32_t h = (uint32_t)e ^ ((uint32_t)(e >> 32) * 0x85EBCA6Bu) ^
+                 (((uint32_t)t * 4u + (uint32_t)k) * 0x9E3779B9u);
+    h ^= h >> 16;
+    h *= 0x7FEB352Du;
+    h ^= h >> 15;
+    h *= 0x846CA68Bu;
+    h ^= h >> 16;
+    return h;
+}
+
+// Word 0 of a tile: its max as binary32 bits, or, when the tile holds a NaN
+// or +inf log-weight, a quiet NaN whose payload is the flags (a clean tile's
+// max is never NaN).
+__device__ __forceinline__ uint32_t pub_max_word(float mx, int fl)
+{
+    return fl ? (0x7FC00000u | (uint32_t)fl) : __float_as_uint(mx);
+}
+
+__device__ __forceinline__ int pub_flags(uint32_t w0)
+{
+    const bool nan = (w0 & 0x7F800000u) == 0x7F800000u && (w0 & 0x007FFFFFu) != 0u;
+    return nan ? (int)(w0 & 0xFFu) : 0;
+}
+
+constexpr int kOnePassWindows = 4;  // overflow windows per block at most
+
+template <int KIND, int DS>
+__global__ __launch_bounds__(kTileThreads) void onepass_kernel(
+    const float *__restrict__ lw, int32_t *__restrict__ anc, int32_t *__restrict__ off, int64_t P,
+    uint64_t seed, uint32_t instance, double *cumw, char *ws_raw, int32_t *status, Rows rows,
+    uint64_t wait_ticks)
+{
+    // Cs (the fill's cumulative weights) and sh_bound (the tile boundaries) in
+    // one array: before the boundaries it holds the tiles' payloads
+    __shared__ double lds_cb[kTile + kOnePassMaxTiles];
+    double *Cs = lds_cb, *sh_bound = lds_cb + kTile;
+    static_assert(3 * kOnePassMaxTiles * sizeof(uint32_t) <= sizeof(lds_cb), "payloads fit");
+    static_assert(kOnePassMaxTiles * (sizeof(int32_t) + 1) <= kChunk * sizeof(int32_t),
+                  "the missing-tile list and bytes fit in sh_anc");
+    __shared__ int32_t sh_anc[kChunk];
+    __shared__ uint64_t sh_epoch;
+    __shared__ int64_t sh_cnt[2 * kOnePassTiles];        // lo, hi of the block's tiles
+    __shared__ int64_t sh_win[kOnePassWindows][3];       // owner tile (-1: none), lo, hi
+    __shared__ int sh_nmiss;
+    extern __shared__ float4 sh_rows4[];  // DS > 0: the block's tiles' rows, kTile x DS floats each
+    constexpr int kRow4 = kTile * (DS > 0 ? DS : 1) / 4;  // float4 per tile of rows
+    static_assert(kTile / 4 == kTileThreads, "one float4 of rows per thread and DS");
+
+    const WsView ws = ws_view(ws_raw, P);
+    const WsLayout L = ws_layout(P, false);
+    uint64_t *epoch = reinterpret_cast<uint64_t *>(ws_raw + L.epoch);
+    uint64_t *pub = reinterpret_cast<uint64_t *>(ws_raw + L.pub);
+    const int64_t n = num_tiles(P), G = gridDim.x, b = blockIdx.x;
+    const int tid = threadIdx.x;
+
+    if (tid == 0) sh_epoch = __hip_atomic_load(epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // every load of the block's own data is issued before the first wait
+    float v[kOnePassTiles][4];
+#pragma unroll
+    for (int r = 0; r < kOnePassTiles; ++r) {
+        const int64_t t = b + r * G;
+        if (t < n) load_tile4(lw, P, t, v[r]);
+        else v[r][0] = v[r][1] = v[r][2] = v[r][3] = -INFINITY;
+    }
+    float4 xs[kOnePassTiles][DS > 0 ? DS : 1];
+    if (DS > 0) {
+        const int64_t total = P * DS;  // floats of state
+#pragma unroll
+        for (int r = 0; r < kOnePassTiles; ++r) {
+            const int64_t t = b + r * G;
+#pragma unroll
+            for (int q = 0; q < DS; ++q) {
+                const int64_t el = t * kTile * DS + 4 * (int64_t)(q * kTileThreads + tid);
+                float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (t < n) {
+                    if (el + 4 <= total) {
+                        x = *reinterpret_cast<const float4 *>(rows.x_in + el);
+                    } else {
+                        if (el + 0 < total) x.x = rows.x_in[el + 0];
+                        if (el + 1 < total) x.y = rows.x_in[el + 1];
+                        if (el + 2 < total) x.z = rows.x_in[el + 2];
+                    }
+                }
+                xs[r][q] = x;
+            }
+        }
+    }
+
+    // ------------------------------------------------ reduce and publish
+#pragma unroll
+    for (int r = 0; r < kOnePassTiles; ++r) {
+        const int64_t t = b + r * G;
+        if (t >= n) break;  // uniform
+        float mx;
+        double s;
+        int fl;
+        tile_reduce_vals(v[r], &mx, &s, &fl);
+        if (tid == 0) {
+            const uint64_t e = sh_epoch;
+            const uint64_t sb = (uint64_t)__double_as_longlong(s);
+            uint64_t *w = pub + 3 * t;
+            __hip_atomic_store(w + 0, ((uint64_t)pub_tag(e, t, 0) << 32) | pub_max_word(mx, fl),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(w + 1, ((uint64_t)pub_tag(e, t, 1) << 32) | (sb >> 32),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(w + 2, ((uint64_t)pub_tag(e, t, 2) << 32) | (sb & 0xFFFFFFFFu),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    if (DS > 0) {
+#pragma unroll
+        for (int r = 0; r < kOnePassTiles; ++r)
+#pragma unroll
+            for (int q = 0; q < DS; ++q) sh_rows4[r * kRow4 + q * kTileThreads + tid] = xs[r][q];
+    }
+
+    // ------------------------------------------------ every tile's values
+    // The 3n words are read as one flat array, 256 consecutive words per
+    // pass of the block (coalesced), and their payloads collected in LDS
+    // (the space of Cs and sh_bound, free until the boundaries); each thread
+    // then takes its own run of tiles from there.
+    constexpr int kPolls = 3 * kOnePassMaxTiles / kTileThreads;  // words per thread at most
+    static_assert(kPolls <= 32, "one mask bit per word");
+    uint32_t *pay = reinterpret_cast<uint32_t *>(lds_cb);  // 3n payloads
+    const uint64_t e = sh_epoch;  // read after the reductions' barriers
+    const int64_t nw = 3 * n;
+    uint32_t need = 0, tag[kPolls];
+#pragma unroll
+    for (int i = 0; i < kPolls; ++i) {
+        const int64_t w = tid + (int64_t)i * kTileThreads;
+        tag[i] = 0;
+        if (w < nw) {
+            need |= 1u << i;
+            tag[i] = pub_tag(e, w / 3, (int)(w % 3));
+        }
+    }
+    const uint64_t start = wall_clock64();
+    bool late = false;
+    while (true) {
+        uint64_t got[kPolls];
+#pragma unroll
+        for (int i = 0; i < kPolls; ++i)
+            if (need & (1u << i))
+                got[i] = __hip_atomic_load(pub + tid + i * kTileThreads, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+        for (int i = 0; i < kPolls; ++i) {
+            if ((need & (1u << i)) && (uint32_t)(got[i] >> 32) == tag[i]) {
+                pay[tid + i * kTileThreads] = (uint32_t)got[i];
+                need &= ~(1u << i);
+            }
+        }
+        if (!__syncthreads_or(need != 0u)) break;
+        if (__syncthreads_or(tid == 0 && wall_clock64() - start > wait_ticks)) {
+            late = true;
+            break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+    if (late) {
+        // reduce the tiles with a word still missing here (the same function,
+        // so the same values); sh_anc holds the list, then a byte per tile
+        uint8_t *miss = reinterpret_cast<uint8_t *>(sh_anc + kOnePassMaxTiles);
+        for (int64_t t = tid; t < n; t += kTileThreads) miss[t] = 0;
+        if (tid == 0) sh_nmiss = 0;
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kPolls; ++i)
+            if (need & (1u << i)) miss[(tid + i * kTileThreads) / 3] = 1;
+        __syncthreads();
+        for (int64_t t = tid; t < n; t += kTileThreads)
+            if (miss[t]) sh_anc[atomicAdd(&sh_nmiss, 1)] = (int32_t)t;
+        __syncthreads();
+        const int nm = sh_nmiss;
+        for (int i = 0; i < nm; ++i) {
+            const int64_t t = sh_anc[i];
+            float vv[4];
+            load_tile4(lw, P, t, vv);
+            float mx;
+            double s;
+            int fl;
+            tile_reduce_vals(vv, &mx, &s, &fl);
+            if (tid == 0) {
+                const uint64_t sb = (uint64_t)__double_as_longlong(s);
+                pay[3 * t] = pub_max_word(mx, fl);
+                pay[3 * t + 1] = (uint32_t)(sb >> 32);
+                pay[3 * t + 2] = (uint32_t)sb;
+            }
+        }
+    }
+    __syncthreads();
+    int64_t t0, t1;
+    bool reg;
+    tile_run(n, &t0, &t1, &reg);  // reg: n <= 1024
+    float mt[kRegTiles];
+    double S[kRegTiles];
+    int fl = 0;
+    float m = -INFINITY;
+#pragma unroll
+    for (int k = 0; k < kRegTiles; ++k) {
+        mt[k] = -INFINITY;
+        S[k] = 0.0;
+        const int64_t t = t0 + k;
+        if (t < t1) {
+            const uint32_t w0 = pay[3 * t];
+            mt[k] = __uint_as_float(w0);
+            fl |= pub_flags(w0);
+            S[k] = __longlong_as_double(
+                (long long)(((uint64_t)pay[3 * t + 1] << 32) | (uint64_t)pay[3 * t + 2]));
+        }
+        m = fmaxf(m, mt[k]);
+    }
+    __syncthreads();  // sh_bound (part of the payload space) is written below
+    // every block read e before publishing, so the counter may move on now
+    if (tid == 0)
+        __hip_atomic_fetch_max(epoch, e + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const TableSums sums = boundaries_tail(ws, n, t0, t1, true, fl, m, mt, S, sh_bound);
+    if (b == 0 && tid == 0) {
+        WsHeader *h = ws.h;
+        h->flags = sums.flags;
+        h->m = sums.m;
+        h->W = sums.W;
+        h->delta = sums.W / (double)P;
+        h->lse = sums.flags
+                     ? ((sums.flags & (kFlagNan | kFlagPosInf)) ? (double)NAN : -(double)INFINITY)
+                     : (double)sums.m + log(sums.W);
+        if (sums.flags) raise_flags(status, sums.flags);
+    }
+    if (sums.flags) {  // flagged input: identity ancestors and rows, one offspring each
+        for (int r = 0; r < kOnePassTiles; ++r) {
+            const int64_t t = b + r * G;
+            for (int64_t j = t * kTile + tid; j < min(P, (t + 1) * kTile); j += kTileThreads) {
+                if (anc) anc[j] = (int32_t)j;
+                if (off) off[j] = 1;
+                if (cumw) cumw[j] = (double)NAN;
+                if (rows.x_in)
+                    for (int d = 0; d < rows.D; ++d)
+                        rows.x_out[j * rows.D + d] = rows.x_in[j * rows.D + d];
+            }
+        }
+        return;
+    }
+    const double W = sums.W, delta = W / (double)P;
+    const float mg = sums.m;  // the largest log-weight (m above is this thread's run's)
+    const double u_sys = KIND == kSystematic ? systematic_offset(seed, instance) : 0.0;
+
+    // ------------------------------------------------ draw counts
+    // the block's tiles: N(B_{t-1}) and N(B_t) on four waves at once
+    const int wave = tid / kWave, lane = tid % kWave;
+    if (lane == 0) {
+        const int r = wave / 2;
+        const int64_t t = b + r * G;
+        if (r < kOnePassTiles && t < n) {
+            const int64_t c = (wave & 1) ? t : t - 1;
+            sh_cnt[wave] = c < 0 ? 0
+                                 : count_below<KIND>(sh_bound[c], P, W, delta, seed, instance,
+                                                     u_sys);
+        }
+    }
+    // overflow windows q = b, b + G, ...: only the tile holding the window's
+    // first draw can own it, and only when more than kChunk - 3 draws fall in
+    // that tile (N(B_t) - N(B_{t-1}) <= (B_t - B_{t-1}) / delta + 2, so tiles
+    // far below that bound are skipped without counting)
+    const int64_t nwin = num_windows(P);
+    if (lane == 32 && wave < kOnePassWindows) {
+        const int64_t q = b + wave * G;
+        int64_t owner = -1, lo_t = 0, hi_t = 0;
+        if (q < nwin) {
+            const double x0 = draw_point<KIND>(q * kWindow, delta, seed, instance, u_sys);
+            const int64_t tt = first_bound_above(sh_bound, n, fmin(x0, below(W)));
+            const double Blo = tt > 0 ? sh_bound[tt - 1] : 0.0;
+            if ((sh_bound[tt] - Blo) / delta + 8.0 > (double)(kChunk - 3)) {
+                hi_t = count_below<KIND>(sh_bound[tt], P, W, delta, seed, instance, u_sys);
+                lo_t = tt > 0 ? count_below<KIND>(Blo, P, W, delta, seed, instance, u_sys) : 0;
+                const int64_t M = (lo_t & ~(int64_t)3) + kChunk;
+                if (max(q * kWindow, M) < min((q + 1) * kWindow, hi_t)) owner = tt;
+            }
+        }
+        sh_win[wave][0] = owner;
+        sh_win[wave][1] = lo_t;
+        sh_win[wave][2] = hi_t;
+    }
+    __syncthreads();
+
+    // ------------------------------------------------ fill the block's tiles
+    for (int r = 0; r < kOnePassTiles; ++r) {
+        const int64_t t = b + r * G;
+        if (t >= n) break;  // uniform
+        const int64_t lo = sh_cnt[2 * r], hi = sh_cnt[2 * r + 1];
+        const int64_t a0 = lo & ~(int64_t)3, oe = min(hi, a0 + kChunk);
+        if (lo >= oe && !cumw && !off) continue;  // no draws and nothing else to write
+        double wts[4];
+        tile_weights(v[r], mg, wts);
+        const float *staged = DS > 0 ? reinterpret_cast<const float *>(sh_rows4 + r * kRow4)
+                                     : nullptr;
+        fill_chunk<KIND>(anc, off, P, seed, instance, cumw, true, t, lo, oe, a0, lo, hi,
+                         t > 0 ? sh_bound[t - 1] : 0.0, sh_bound[t], W, wts, rows.x_in,
+                         rows.x_out, rows.D, status, Cs, sh_anc, staged);
+        __syncthreads();  // Cs and sh_anc are reused
+    }
+    // ------------------------------------------------ overflow windows owned
+    for (int k = 0; k < kOnePassWindows; ++k) {
+        const int64_t t = sh_win[k][0];
+        if (t < 0) continue;  // uniform
+        const int64_t q = b + k * G, lo = sh_win[k][1], hi = sh_win[k][2];
+        const int64_t ob = max(q * kWindow, (lo & ~(int64_t)3) + kChunk);
+        const int64_t oe = min((q + 1) * kWindow, hi), a0 = ob & ~(int64_t)3;
+        float vv[4];
+        double wts[4];
+        load_tile4(lw, P, t, vv);
+        tile_weights(vv, mg, wts);
+        fill_chunk<KIND>(anc, off, P, seed, instance, cumw, false, t, ob, oe, a0, lo, hi,
+                         t > 0 ? sh_bound[t - 1] : 0.0, sh_bound[t], W, wts, rows.x_in,
+                         rows.x_out, rows.D, status, Cs, sh_anc, nullptr);
+        __syncthreads();
+    }
 }
 
 // Guide table of the multinomial search (Chen and Asau's method for
@@ -706,6 +1054,119 @@ __global__ __launch_bounds__(kTileThreads) void multinomial_small_kernel(
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
+namespace {
+std::atomic<int> g_prefix_path{kPathAuto};
+std::atomic<int64_t> g_onepass_wait_ns{-1};
+constexpr int64_t kOnePassWaitNs = 100000;  // bound of a block's wait for the others' tiles
+
+struct OnePassDevice {
+    int64_t capacity[3] = {-1, -1, -1};  // co-resident blocks per row width (0, 1-2, 4)
+    int64_t ticks_per_ms = 0;            // real-time clock
+};
+std::mutex g_onepass_mutex;
+OnePassDevice g_onepass_dev[64];
+
+template <int KIND, int DS>
+const void *onepass_fn()
+{
+    return reinterpret_cast<const void *>(&onepass_kernel<KIND, DS>);
+}
+
+size_t onepass_smem(int DS) { return (size_t)kOnePassTiles * kTile * DS * sizeof(float); }
+
+// Blocks of onepass_kernel<KIND, DS> the device holds at once, and the
+// real-time clock rate; 0 capacity: unknown (the caller uses the launches).
+int onepass_device(const void *fn, int slot, size_t smem, int64_t *capacity, int64_t *ticks_per_ms)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return record_hip_error(e);
+    if (dev < 0 || dev >= 64) {
+        *capacity = 0;
+        return 0;
+    }
+    std::lock_guard<std::mutex> lock(g_onepass_mutex);
+    OnePassDevice &d = g_onepass_dev[dev];
+    if (d.capacity[slot] < 0) {
+        int per_cu = 0, cus = 0, khz = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kTileThreads, smem);
+        if (e != hipSuccess) return record_hip_error(e);
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return record_hip_error(e);
+        e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+        if (e != hipSuccess) return record_hip_error(e);
+        d.capacity[slot] = (int64_t)per_cu * cus;
+        d.ticks_per_ms = khz;
+    }
+    *capacity = d.capacity[slot];
+    *ticks_per_ms = d.ticks_per_ms;
+    return 0;
+}
+
+// Launches the one-pass stratified/systematic kernel when the call qualifies
+// (at most kOnePassMaxTiles tiles, enough co-resident blocks, the path
+// setting allows it). *done = false: the caller runs the launches instead.
+template <int KIND>
+int try_onepass(const float *lw, int32_t *anc, int32_t *off, int64_t P, uint64_t seed,
+                uint32_t instance, double *cumw, char *w, int32_t *status, hipStream_t stream,
+                const Rows &rows, bool *done)
+{
+    *done = false;
+    const int path = g_prefix_path.load();
+    const int64_t n = num_tiles(P);
+    if (path != kPathOnePass || n > kOnePassMaxTiles) return 0;  // auto: the launches (faster)
+    const int64_t G = (n + kOnePassTiles - 1) / kOnePassTiles;
+    if (num_windows(P) > (int64_t)kOnePassWindows * G) return 0;
+    const bool staged = rows.x_in && (rows.D == 1 || rows.D == 2 || rows.D == 4) &&
+                        (((uintptr_t)rows.x_in) & 15) == 0;
+    const int DS = staged ? rows.D : 0;
+    const void *fn;
+    int slot;
+    if (DS == 0) fn = onepass_fn<KIND, 0>(), slot = 0;
+    else if (DS == 1) fn = onepass_fn<KIND, 1>(), slot = 1;
+    else if (DS == 2) fn = onepass_fn<KIND, 2>(), slot = 1;
+    else fn = onepass_fn<KIND, 4>(), slot = 2;
+    const size_t smem = onepass_smem(DS);
+    int64_t capacity = 0, ticks_per_ms = 0;
+    if (const int rc = onepass_device(fn, slot, smem, &capacity, &ticks_per_ms)) return rc;
+    if (G > capacity) return 0;
+    const int64_t wait_ns = g_onepass_wait_ns.load() < 0 ? kOnePassWaitNs : g_onepass_wait_ns.load();
+    const uint64_t ticks = (uint64_t)(wait_ns * ticks_per_ms / 1000000);
+    if (smem && allow_dynamic_lds(fn, smem)) return -3;
+    const dim3 grid((uint32_t)G), tb(kTileThreads);
+    switch (DS) {
+    case 0:
+        hipLaunchKernelGGL((onepass_kernel<KIND, 0>), grid, tb, smem, stream, lw, anc, off, P, seed,
+                           instance, cumw, w, status, rows, ticks);
+        break;
+    case 1:
+        hipLaunchKernelGGL((onepass_kernel<KIND, 1>), grid, tb, smem, stream, lw, anc, off, P, seed,
+                           instance, cumw, w, status, rows, ticks);
+        break;
+    case 2:
+        hipLaunchKernelGGL((onepass_kernel<KIND, 2>), grid, tb, smem, stream, lw, anc, off, P, seed,
+                           instance, cumw, w, status, rows, ticks);
+        break;
+    default:
+        hipLaunchKernelGGL((onepass_kernel<KIND, 4>), grid, tb, smem, stream, lw, anc, off, P, seed,
+                           instance, cumw, w, status, rows, ticks);
+        break;
+    }
+    *done = true;
+    return 0;
+}
+}  // namespace
+
+int set_prefix_path(int path, int64_t wait_ns)
+{
+    if (path != kPathAuto && path != kPathLaunches && path != kPathOnePass) return -1;
+    g_prefix_path.store(path);
+    g_onepass_wait_ns.store(wait_ns < 0 ? -1 : wait_ns);
+    return 0;
+}
+
+int get_prefix_path() { return g_prefix_path.load(); }
+
 int launch_prefix(int kind, const float *lw, int32_t *anc, int32_t *off, int64_t P, uint64_t seed,
                   uint32_t instance, double *cumw, void *ws, int32_t *status,
                   hipStream_t stream, const Rows &rows)
@@ -718,6 +1179,16 @@ int launch_prefix(int kind, const float *lw, int32_t *anc, int32_t *off, int64_t
         hipLaunchKernelGGL(multinomial_small_kernel, dim3(1), tb, 0, stream, lw, anc, P, seed,
                            instance, C, w, status, rows);
         return launch_status();
+    }
+    if (kind == kStratified || kind == kSystematic) {
+        bool done = false;
+        const int rc = kind == kStratified
+                           ? try_onepass<kStratified>(lw, anc, off, P, seed, instance, cumw, w,
+                                                      status, stream, rows, &done)
+                           : try_onepass<kSystematic>(lw, anc, off, P, seed, instance, cumw, w,
+                                                      status, stream, rows, &done);
+        if (rc) return rc;
+        if (done) return launch_status();
     }
     hipLaunchKernelGGL(tile_reduce_kernel, dim3((uint32_t)n), tb, 0, stream, lw, P, w);
     switch (kind) {

@@ -189,15 +189,13 @@ __device__ int64_t count_below(double c, int64_t P, double W, double delta, uint
 }
 
 // ------------------------------------------------------ phase 1: tile
-__device__ inline void tile_reduce_body(const float *__restrict__ lw, int64_t P, int64_t t,
-                                        char *ws_raw)
+// A tile's max, sum of exp(lw - max) in binary64 and data flags from the
+// block's four log-weights per thread (every thread gets the results).
+__device__ inline void tile_reduce_vals(const float v[4], float *mx_out, double *s_out, int *fl_out)
 {
     __shared__ double redd[kNW];
     __shared__ float redf[kNW];
     __shared__ int redi[kNW];
-    const WsView ws = ws_view(ws_raw, P);
-    float v[4];
-    load_tile4(lw, P, t, v);
     int fl = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -225,7 +223,21 @@ __device__ inline void tile_reduce_body(const float *__restrict__ lw, int64_t P,
 #pragma unroll
         for (int k = 0; k < 4; ++k) s += exp((double)v[k] - (double)mx);
     }
-    s = block_sum(s, redd);
+    *s_out = block_sum(s, redd);
+    *mx_out = mx;
+    *fl_out = fl;
+}
+
+__device__ inline void tile_reduce_body(const float *__restrict__ lw, int64_t P, int64_t t,
+                                        char *ws_raw)
+{
+    const WsView ws = ws_view(ws_raw, P);
+    float v[4];
+    load_tile4(lw, P, t, v);
+    float mx;
+    double s;
+    int fl;
+    tile_reduce_vals(v, &mx, &s, &fl);
     if (threadIdx.x == 0) {
         ws.tile_max[t] = mx;
         ws.tile_sum[t] = s;
@@ -254,21 +266,35 @@ struct TableSums {
 constexpr int kRegTiles = 4;
 constexpr int kRunBatch = 8;  // a thread's run is read this many entries at a time
 
-__device__ inline TableSums boundaries(const WsView &ws, int64_t P, double *bound)
+// The boundaries once each thread holds its run's tile values: in
+// registers (reg: mt, S for tiles t0 .. t1-1, at most kRegTiles) or, for
+// longer runs, the sums in bound[] and the maxima in ws.tile_max; fl and m
+// are the thread's OR of flags and max over its run.
+__device__ __forceinline__ TableSums boundaries_tail(const WsView &ws, int64_t n, int64_t t0, int64_t t1,
+                                            bool reg, int fl, float m, float mt[kRegTiles],
+                                            double S[kRegTiles], double *bound);
+
+// The thread's run of tiles for boundaries(): [t0, t1), and whether it fits
+// in registers.
+__device__ __forceinline__ void tile_run(int64_t n, int64_t *t0, int64_t *t1, bool *reg)
 {
-    __shared__ double redd[kNW];
-    __shared__ float redf[kNW];
-    __shared__ int redi[kNW];
-    __shared__ double sh_W;
-    const int64_t n = num_tiles(P);
-    const int tid = threadIdx.x;
     int64_t per = (n + kTileThreads - 1) / kTileThreads;
-    const bool reg = per <= kRegTiles;  // uniform
+    *reg = per <= kRegTiles;  // uniform
     // Longer runs get an odd length, so that the 64 runs of a wave start in
     // different LDS banks (an even length in doubles puts every lane's k-th
     // element in the same bank).
-    if (!reg) per |= 1;
-    const int64_t t0 = min(n, (int64_t)tid * per), t1 = min(n, t0 + per);
+    if (!*reg) per |= 1;
+    *t0 = min(n, (int64_t)threadIdx.x * per);
+    *t1 = min(n, *t0 + per);
+}
+
+__device__ inline TableSums boundaries(const WsView &ws, int64_t P, double *bound)
+{
+    const int64_t n = num_tiles(P);
+    const int tid = threadIdx.x;
+    int64_t t0, t1;
+    bool reg;
+    tile_run(n, &t0, &t1, &reg);
     int fl = 0;
     float m = -INFINITY;
     float mt[kRegTiles];
@@ -308,6 +334,18 @@ __device__ inline TableSums boundaries(const WsView &ws, int64_t P, double *boun
             bound[t] = ws.tile_sum[t];
         }
     }
+    return boundaries_tail(ws, n, t0, t1, reg, fl, m, mt, S, bound);
+}
+
+__device__ __forceinline__ TableSums boundaries_tail(const WsView &ws, int64_t n, int64_t t0, int64_t t1,
+                                            bool reg, int fl, float m, float mt[kRegTiles],
+                                            double S[kRegTiles], double *bound)
+{
+    __shared__ double redd[kNW];
+    __shared__ float redf[kNW];
+    __shared__ int redi[kNW];
+    __shared__ double sh_W;
+    const int tid = threadIdx.x;
     // flags and max in one barrier (redi/redf are next written after later barriers)
     fl = wave_or(fl);
     m = wave_max(m);
@@ -579,6 +617,39 @@ __device__ inline void copy_rows_from_lds(const int32_t *sh_anc, int64_t a0, int
     }
 }
 
+// As copy_rows_from_lds, with the source rows of tile t (particles
+// tile_base .. tile_base + kTile - 1) staged in LDS: x_out[o, :] =
+// sh_rows[(a_o - tile_base) D ..]. The fill's ancestors lie in its tile.
+__device__ inline void copy_rows_staged(const int32_t *sh_anc, int64_t a0, int64_t ob, int64_t oe,
+                                        const float *sh_rows, int64_t tile_base,
+                                        float *__restrict__ x_out, int32_t D, int *fl)
+{
+    const bool vec = (D % 4 == 0) && ((((uintptr_t)x_out) & 15) == 0);
+    if (vec) {
+        const int cols = D / 4;
+        const int64_t total = (oe - ob) * cols;
+        for (int64_t e = threadIdx.x; e < total; e += kTileThreads) {
+            const int64_t r = e / cols, c = e - r * cols;
+            const int64_t o = ob + r;
+            const int64_t a = (int64_t)sh_anc[o - a0] - tile_base;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (a >= 0 && a < kTile) v = reinterpret_cast<const float4 *>(sh_rows)[a * cols + c];
+            else *fl |= kFlagInternal;
+            reinterpret_cast<float4 *>(x_out)[o * cols + c] = v;
+        }
+    } else {
+        const int64_t total = (oe - ob) * D;
+        for (int64_t e = threadIdx.x; e < total; e += kTileThreads) {
+            const int64_t r = e / D, d = e - r * D;
+            const int64_t o = ob + r;
+            const int64_t a = (int64_t)sh_anc[o - a0] - tile_base;
+            const bool ok = a >= 0 && a < kTile;
+            x_out[o * D + d] = ok ? sh_rows[a * D + d] : 0.0f;
+            if (!ok) *fl |= kFlagInternal;
+        }
+    }
+}
+
 // ------------------------------------------------------ phase 3: fill
 // First tile t with B_t > x, for x < W (bisection over n non-decreasing
 // boundaries in LDS).
@@ -665,6 +736,93 @@ __device__ void tile_offspring(int32_t *off, int64_t P, int64_t t, int64_t lo, i
 #pragma unroll
         for (int k = 0; k < 4; ++k)
             if (j0 + k < P) off[j0 + k] = o[k];
+    }
+}
+
+// The fill proper, shared by the fill launch and the one-pass launch: the
+// block's draw slots [ob, oe) of tile t (slot base a0; the tile's draws are
+// [lo, hi), its boundaries Blo and Bhi, wts the thread's four weights
+// exp(lw - m)): the tile's cumulative weights in Cs (stored to cumw by a
+// tile block), the ancestors of the slots, the tile's offspring (tile block)
+// and the rows (from sh_rows, the tile's kTile rows staged in LDS, when given).
+template <int KIND>
+__device__ __forceinline__ void fill_chunk(int32_t *__restrict__ anc, int32_t *__restrict__ off, int64_t P,
+                           uint64_t seed, uint32_t instance, double *cumw, bool tile_block,
+                           int64_t t, int64_t ob, int64_t oe, int64_t a0, int64_t lo, int64_t hi,
+                           double Blo, double Bhi, double W, const double wts[4],
+                           const float *x_in, float *x_out, int32_t D, int32_t *status,
+                           double *Cs, int32_t *sh_anc, const float *sh_rows)
+{
+    const double delta = W / (double)P;
+    const double u_sys = KIND == kSystematic ? systematic_offset(seed, instance) : 0.0;
+    const bool want_off = off && tile_block;
+    double C[4];
+    tile_cumulative(wts, Blo, Bhi, Cs, C);  // ends with a barrier
+    if (cumw && tile_block) store_cumw(cumw, P, t, C);
+
+    const bool keep = x_in || want_off;  // ancestors needed again from LDS
+    const int64_t o0 = a0 + 8 * (int64_t)threadIdx.x;
+    int32_t a[8];  // this thread's slots' ancestors (defined for the slots in [ob, oe))
+    if (o0 + 8 > ob && o0 < oe) {
+        double U[8];
+        if (KIND == kStratified) {
+            const Block4 b0 = philox(seed, (uint32_t)(o0 >> 2), instance, 0u, kTagStratified);
+            const Block4 b1 = philox(seed, (uint32_t)(o0 >> 2) + 1u, instance, 0u, kTagStratified);
+            U[0] = unit32(b0.r0); U[1] = unit32(b0.r1); U[2] = unit32(b0.r2); U[3] = unit32(b0.r3);
+            U[4] = unit32(b1.r0); U[5] = unit32(b1.r1); U[6] = unit32(b1.r2); U[7] = unit32(b1.r3);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) U[k] = u_sys;
+        }
+        const double cap = below(Bhi);
+        double x[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) x[k] = fmin(((double)(o0 + k) + U[k]) * delta, cap);
+        // the draws are non-decreasing, so a_0 <= a_k <= a_7: bisect the whole
+        // tile for the first and last draw only, and the six between within
+        // [a_0, a_7] (usually a few particles), all six in lockstep; the same
+        // first-above rule, so the same ancestors as eight full bisections
+        const int32_t tile_base = (int32_t)(t * kTile);
+        const int j0 = search_tile(Cs, x[0]), j7 = search_tile(Cs, x[7]);
+        int jm[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) jm[k] = j0;
+        for (int len = j7 - j0 + 1; len > 1;) {
+            const int half = len >> 1;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) jm[k] = Cs[jm[k] + half - 1] <= x[k + 1] ? jm[k] + half : jm[k];
+            len -= half;
+        }
+        a[0] = tile_base + j0;
+        a[7] = tile_base + j7;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) a[k + 1] = tile_base + jm[k];
+        if (anc) {
+            const bool full = (o0 >= ob) && (o0 + 8 <= oe) && ((((uintptr_t)(anc + o0)) & 15) == 0);
+            if (full) {
+                int4 *dst = reinterpret_cast<int4 *>(anc + o0);
+                dst[0] = make_int4(a[0], a[1], a[2], a[3]);
+                dst[1] = make_int4(a[4], a[5], a[6], a[7]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    if (o0 + k >= ob && o0 + k < oe) anc[o0 + k] = a[k];
+            }
+        }
+        if (keep) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) sh_anc[8 * threadIdx.x + k] = a[k];
+        }
+    }
+    if (keep) __syncthreads();
+    if (want_off)
+        tile_offspring<KIND>(off, P, t, lo, hi, oe, a0, a, sh_anc, Cs, W,
+                             delta, seed, instance, u_sys);
+    if (x_in) {
+        int fl = 0;
+        if (sh_rows) copy_rows_staged(sh_anc, a0, ob, oe, sh_rows, t * kTile, x_out, D, &fl);
+        else copy_rows_from_lds(sh_anc, a0, ob, oe, x_in, x_out, D, P, &fl);
+        raise_flags(status, fl);
     }
 }
 
@@ -831,73 +989,8 @@ __device__ void fill_body(const float *__restrict__ lw, int32_t *__restrict__ an
         tile_weights(v, m, wts);
     }
 
-    double C[4];
-    tile_cumulative(wts, Blo, Bhi, Cs, C);  // ends with a barrier
-    if (cumw && tile_block) store_cumw(cumw, P, t, C);
-
-    const bool keep = x_in || want_off;  // ancestors needed again from LDS
-    const int64_t o0 = a0 + 8 * (int64_t)threadIdx.x;
-    int32_t a[8];  // this thread's slots' ancestors (defined for the slots in [ob, oe))
-    if (o0 + 8 > ob && o0 < oe) {
-        double U[8];
-        if (KIND == kStratified) {
-            const Block4 b0 = philox(seed, (uint32_t)(o0 >> 2), instance, 0u, kTagStratified);
-            const Block4 b1 = philox(seed, (uint32_t)(o0 >> 2) + 1u, instance, 0u, kTagStratified);
-            U[0] = unit32(b0.r0); U[1] = unit32(b0.r1); U[2] = unit32(b0.r2); U[3] = unit32(b0.r3);
-            U[4] = unit32(b1.r0); U[5] = unit32(b1.r1); U[6] = unit32(b1.r2); U[7] = unit32(b1.r3);
-        } else {
-#pragma unroll
-            for (int k = 0; k < 8; ++k) U[k] = u_sys;
-        }
-        const double cap = below(Bhi);
-        double x[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) x[k] = fmin(((double)(o0 + k) + U[k]) * delta, cap);
-        // the draws are non-decreasing, so a_0 <= a_k <= a_7: bisect the whole
-        // tile for the first and last draw only, and the six between within
-        // [a_0, a_7] (usually a few particles), all six in lockstep; the same
-        // first-above rule, so the same ancestors as eight full bisections
-        const int32_t tile_base = (int32_t)(t * kTile);
-        const int j0 = search_tile(Cs, x[0]), j7 = search_tile(Cs, x[7]);
-        int jm[6];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) jm[k] = j0;
-        for (int len = j7 - j0 + 1; len > 1;) {
-            const int half = len >> 1;
-#pragma unroll
-            for (int k = 0; k < 6; ++k) jm[k] = Cs[jm[k] + half - 1] <= x[k + 1] ? jm[k] + half : jm[k];
-            len -= half;
-        }
-        a[0] = tile_base + j0;
-        a[7] = tile_base + j7;
-#pragma unroll
-        for (int k = 0; k < 6; ++k) a[k + 1] = tile_base + jm[k];
-        if (anc) {
-            const bool full = (o0 >= ob) && (o0 + 8 <= oe) && ((((uintptr_t)(anc + o0)) & 15) == 0);
-            if (full) {
-                int4 *dst = reinterpret_cast<int4 *>(anc + o0);
-                dst[0] = make_int4(a[0], a[1], a[2], a[3]);
-                dst[1] = make_int4(a[4], a[5], a[6], a[7]);
-            } else {
-#pragma unroll
-                for (int k = 0; k < 8; ++k)
-                    if (o0 + k >= ob && o0 + k < oe) anc[o0 + k] = a[k];
-            }
-        }
-        if (keep) {
-#pragma unroll
-            for (int k = 0; k < 8; ++k) sh_anc[8 * threadIdx.x + k] = a[k];
-        }
-    }
-    if (keep) __syncthreads();
-    if (want_off)
-        tile_offspring<KIND>(off, P, t, sh_range[4], sh_range[5], oe, a0, a, sh_anc, Cs, W,
-                             delta, seed, instance, u_sys);
-    if (x_in) {
-        int fl = 0;
-        copy_rows_from_lds(sh_anc, a0, ob, oe, x_in, x_out, D, P, &fl);
-        raise_flags(status, fl);
-    }
+    fill_chunk<KIND>(anc, off, P, seed, instance, cumw, tile_block, t, ob, oe, a0, sh_range[4],
+                     sh_range[5], Blo, Bhi, W, wts, x_in, x_out, D, status, Cs, sh_anc, nullptr);
 }
 
 }  // namespace pfx
