@@ -99,6 +99,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--only", type=str, default="", help="time one kernel (for profiling)")
     ap.add_argument("--out", type=str, default=os.path.join("gpurun_out", "bench_full.json"))
+    ap.add_argument("--record-traffic", type=str, default="",
+                    help="write profiles/traffic.json from the rocprofv3 counter runs under "
+                         "this directory (subdirectories <family>_<COUNTER>) and exit")
     return ap.parse_args()
 
 
@@ -133,6 +136,9 @@ SIGMA_OF_SETS = 1.0
 
 def main():
     args = parse()
+    if args.record_traffic:
+        record_traffic(args.record_traffic)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU sharding is "
                                    "a design only, not built", "n_gpus": args.gpus}))
@@ -326,6 +332,9 @@ def profile_only(torch, rs, args, sets, families, step):
     only["copycal"] = lambda bs, k: big_out.copy_(big)
     only["step"] = lambda bs, k: step(bs, k, 0)
     only["permute_copy"] = only["permute_copy_sorted"]
+    probe_out = torch.empty(1 << 20, dtype=torch.float32, device=sets[0]["lw"].device)
+    only["gather_probe"] = lambda bs, k: rs.rs_probe_gather(sets[0]["lw"], 1 << 20, 8, k + 1,
+                                                           out=probe_out)
     fn = only[args.only]
     for bs in sets:  # sorted ancestors for the copy
         rs.resample_stratified(bs["lw"], 1, 0, anc=bs["anc"], ws=rs.workspace(bs["lw"].numel(),
@@ -523,6 +532,66 @@ def load_traffic(kernel):
     if not entry or entry.get("source_sha256") != source_hash(kernel):
         return None
     return entry.get("bytes_per_launch")
+
+
+# Kernels of each call family, by a part of their names (the --only runs also
+# launch set-up stratified calls, whose table and fill kernels are left out
+# of the other families).
+FAMILY_KERNELS = {
+    "copycal": ["copyBuffer"],
+    "metropolis": ["metropolis_kernel"],
+    "permute_copy": ["copy_rows"],
+    "stratified": ["tile_reduce_kernel", "table_kernel<0", "fill_kernel<0"],
+    "multinomial": ["tile_reduce_kernel", "cumulative_kernel", "multinomial_search_kernel"],
+}
+CALIBRATION_BYTES = 64 << 20  # the copycal run copies 64 MiB per dispatch
+
+
+def record_traffic(pmc_dir):
+    """profiles/traffic.json from rocprofv3 --pmc runs of `bench.py --only X`
+    (one counter per run, directories <family>_<COUNTER>): per kernel the
+    counter's mean per dispatch, scaled by what the same counter reads for a
+    plain 64 MiB copy, and per family the sum over its kernels."""
+    import csv
+    import glob
+
+    def per_dispatch(family, counter):
+        files = glob.glob(os.path.join(pmc_dir, f"{family}_{counter}", "**",
+                                       "*counter_collection.csv"), recursive=True)
+        vals = {}
+        for path in files:
+            with open(path, newline="") as f:
+                for row in csv.DictReader(f):
+                    if row.get("Counter_Name") != counter:
+                        continue
+                    name = row["Kernel_Name"]
+                    if any(k in name for k in FAMILY_KERNELS[family]):
+                        vals.setdefault(name, {}).setdefault(row.get("Dispatch_Id"), 0.0)
+                        vals[name][row.get("Dispatch_Id")] += float(row["Counter_Value"])
+        return {name: float(np.mean(list(d.values()))) for name, d in vals.items()}
+
+    rec = {"_calibration": {}}
+    factor = {}
+    for counter in ("FETCH_SIZE", "WRITE_SIZE"):
+        cal = per_dispatch("copycal", counter)
+        kib = float(np.mean(list(cal.values())))
+        factor[counter] = CALIBRATION_BYTES / (kib * 1024.0)
+        rec["_calibration"][counter] = {"factor": factor[counter], "kernel": "copyBuffer (torch)",
+                                        "KiB_per_dispatch": kib}
+    for family in ("metropolis", "permute_copy", "stratified", "multinomial"):
+        kernels = {}
+        for counter in ("FETCH_SIZE", "WRITE_SIZE"):
+            for name, kib in per_dispatch(family, counter).items():
+                kernels.setdefault(name[:80], {})[counter] = kib * 1024.0 * factor[counter]
+        if not kernels:
+            continue
+        total = sum(sum(v.values()) for v in kernels.values())
+        rec[family] = {"bytes_per_launch": total, "kernels": kernels,
+                       "source_sha256": source_hash(family)}
+        log(f"traffic: {family} {total / 1e6:.2f} MB per call")
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
+        json.dump(rec, f, indent=1)
+        f.write("\n")
 
 
 # The sources each kernel family is compiled from (what invalidates its counters).
