@@ -57,6 +57,7 @@ def _load():
         "oracle_ancestors_to_offspring": (ctypes.c_int, [i32p, i32p, i64]),
         "oracle_offspring_to_ancestors": (ctypes.c_int, [i32p, i32p, i64]),
         "oracle_permute_copy": (ctypes.c_int, [i32p, f32p, f32p, i64, i32]),
+        "oracle_offspring_update_inplace": (ctypes.c_int, [i32p, f32p, i64, i32, i32p]),
         "oracle_metropolis_B": (u32, [i64, ctypes.c_double, ctypes.c_double]),
         "oracle_resampling_error": (ctypes.c_double, [i32p, f32p, i64]),
         "oracle_filter_init": (ctypes.c_int, [f32p, i64, i32, u64]),
@@ -272,6 +273,21 @@ def permute_copy(anc, x_in):
     rc = _check(_lib.oracle_permute_copy(_ptr(anc, ctypes.c_int32), _ptr(x_in, ctypes.c_float),
                                          _ptr(out, ctypes.c_float), P, D), "permute_copy")
     return out, rc
+
+
+def offspring_update_inplace(off, x):
+    """The minimal-copy update (resample_oracle.c): returns (x updated, the
+    particle each slot holds afterwards, flags); x itself is not modified."""
+    off = _i32(off)
+    x = _f32(x).copy()
+    P = off.size
+    D = x.size // P
+    anc = np.empty(P, dtype=np.int32)
+    rc = _check(_lib.oracle_offspring_update_inplace(_ptr(off, ctypes.c_int32),
+                                                     _ptr(x, ctypes.c_float), P, D,
+                                                     _ptr(anc, ctypes.c_int32)),
+                "offspring_update_inplace")
+    return x, anc, rc
 
 
 def metropolis_B(P, w_max, eps):

@@ -412,6 +412,48 @@ int oracle_permute_copy(const int32_t *anc, const float *x_in, float *x_out, int
     return bad ? ORACLE_FLAG_BAD_ANCESTOR : 0;
 }
 
+/*
+ * Minimal-copy state update from offspring counts (Sec. 2 gives the output
+ * of a resampler as offspring o_j, the number of copies of particle j in the
+ * new population, and says converting between offspring and ancestors is
+ * straightforward). After resampling every particle carries weight 1 / P,
+ * so the new population is defined by its multiset {x_j repeated o_j times};
+ * the slot order is free. This update keeps every row j with o_j >= 1 in its
+ * own slot and fills each empty slot (o_i = 0) with one of the extra copies
+ * (o_j - 1 of them for each j with o_j >= 2): the holes in increasing slot
+ * order take the extras in increasing order of j. A source j is never a
+ * hole, so the update can be done in place. anc_out[i] is the particle whose
+ * row slot i holds afterwards. Counts that are negative or do not sum to P
+ * leave x unchanged, anc_out the identity, and return the bad-ancestor flag.
+ */
+int oracle_offspring_update_inplace(const int32_t *off, float *x, int64_t P, int32_t D,
+                                    int32_t *anc_out)
+{
+    if (!off || !x || !anc_out || P < 1 || D < 1) return ORACLE_EINVAL;
+    int64_t total = 0;
+    for (int64_t j = 0; j < P; ++j) {
+        if (off[j] < 0) total = -1;
+        if (total >= 0) total += off[j];
+    }
+    for (int64_t i = 0; i < P; ++i) anc_out[i] = (int32_t)i;
+    if (total != P) return ORACLE_FLAG_BAD_ANCESTOR;
+    /* walk the holes and the extra copies together, both in increasing order */
+    int64_t j = 0;     /* current source particle */
+    int32_t used = 0;  /* extra copies of j already placed */
+    for (int64_t i = 0; i < P; ++i) {
+        if (off[i] != 0) continue;
+        while (j < P && off[j] - 1 - used <= 0) {  /* no extra copy of j left */
+            ++j;
+            used = 0;
+        }
+        if (j >= P) return ORACLE_EINVAL;  /* not reached when the counts sum to P */
+        anc_out[i] = (int32_t)j;
+        memcpy(x + i * (int64_t)D, x + j * (int64_t)D, (size_t)D * sizeof(float));
+        ++used;
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Number of Metropolis iterations B (Sec. 2, eqs. (1)-(5)): the two-state   */
 /* chain Z_n on "is the chain at p_max" has alpha = (1 - w_max) / (P w_max), */
