@@ -260,6 +260,7 @@ def main():
         sections.append(("sweep", lambda: sweep(torch, rs, workloads, args)))
     if not args.no_batch:
         sections.append(("batched", lambda: batched(torch, rs, workloads, args)))
+    sections.append(("minimal_copy", lambda: minimal_copy(torch, rs, workloads, P, B_eq5)))
     if not args.no_dirichlet:
         sections.append(("dirichlet", lambda: dirichlet(torch, rs, workloads, args)))
     if not args.no_filter:
@@ -333,12 +334,21 @@ def profile_only(torch, rs, args, sets, families, step):
     only["step"] = lambda bs, k: step(bs, k, 0)
     only["permute_copy"] = only["permute_copy_sorted"]
     probe_out = torch.empty(1 << 20, dtype=torch.float32, device=sets[0]["lw"].device)
+    ip_ws = torch.empty(int(rs.lib.rs_inplace_workspace_bytes(sets[0]["lw"].numel())),
+                        dtype=torch.uint8, device=sets[0]["lw"].device)
+    only["inplace"] = lambda bs, k: rs.offspring_update_inplace(bs["off"], bs["x"], ws=ip_ws)
     only["gather_probe"] = lambda bs, k: rs.rs_probe_gather(sets[0]["lw"], 1 << 20, 8, k + 1,
                                                            out=probe_out)
+    only["permute_copy_metropolis"] = only["permute_copy_random"]
     fn = only[args.only]
-    for bs in sets:  # sorted ancestors for the copy
-        rs.resample_stratified(bs["lw"], 1, 0, anc=bs["anc"], ws=rs.workspace(bs["lw"].numel(),
-                                                                           rs.MULTINOMIAL))
+    for k, bs in enumerate(sets):
+        if args.only in ("inplace", "permute_copy_metropolis"):
+            # Metropolis ancestors (eq. (5)'s B) and their offspring
+            families["metropolis"][0](bs, 900 + k)
+            rs.ancestors_to_offspring(bs["anc"], off=bs["off"])
+        else:  # sorted ancestors for the copy
+            rs.resample_stratified(bs["lw"], 1, 0, anc=bs["anc"],
+                                   ws=rs.workspace(bs["lw"].numel(), rs.MULTINOMIAL))
     for k in range(args.warmup):
         fn(sets[k % len(sets)], k)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -425,6 +435,11 @@ def headline(full, out_path):
         b = full["batched"]
         h["batched"] = {"ms_p50": b["batched_ms_p50"],
                         "speedup_vs_per_instance_graph": b["speedup_vs_per_instance_graph"]}
+    if "minimal_copy" in full:
+        h["minimal_copy"] = {k: {m: v[m] for m in ("permute_copy_us", "inplace_us",
+                                                     "anc_to_off_plus_inplace_us",
+                                                     "bytes_ratio_vs_permute_copy")}
+                             for k, v in full["minimal_copy"].items() if k.startswith("D")}
     if "serving" in full:
         h["serving"] = {name: {k: pt.get(k) for k in ("rate_req_per_s", "p50_latency_ms",
                                                       "p99_latency_ms", "particles_per_s",
@@ -543,6 +558,8 @@ FAMILY_KERNELS = {
     "permute_copy": ["copy_rows"],
     "stratified": ["tile_reduce_kernel", "table_kernel<0", "fill_kernel<0"],
     "multinomial": ["tile_reduce_kernel", "cumulative_kernel", "multinomial_search_kernel"],
+    "inplace": ["ip_count_kernel", "ip_table_kernel", "ip_move_kernel"],
+    "permute_copy_metropolis": ["copy_rows"],
 }
 CALIBRATION_BYTES = 64 << 20  # the copycal run copies 64 MiB per dispatch
 
@@ -570,15 +587,22 @@ def record_traffic(pmc_dir):
                         vals[name][row.get("Dispatch_Id")] += float(row["Counter_Value"])
         return {name: float(np.mean(list(d.values()))) for name, d in vals.items()}
 
-    rec = {"_calibration": {}}
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:  # families not measured in this directory keep their entries
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        rec = {}
     factor = {}
     for counter in ("FETCH_SIZE", "WRITE_SIZE"):
         cal = per_dispatch("copycal", counter)
-        kib = float(np.mean(list(cal.values())))
-        factor[counter] = CALIBRATION_BYTES / (kib * 1024.0)
-        rec["_calibration"][counter] = {"factor": factor[counter], "kernel": "copyBuffer (torch)",
-                                        "KiB_per_dispatch": kib}
-    for family in ("metropolis", "permute_copy", "stratified", "multinomial"):
+        if cal:
+            kib = float(np.mean(list(cal.values())))
+            rec.setdefault("_calibration", {})[counter] = {
+                "factor": CALIBRATION_BYTES / (kib * 1024.0), "kernel": "copyBuffer (torch)",
+                "KiB_per_dispatch": kib}
+        factor[counter] = rec["_calibration"][counter]["factor"]
+    for family in ("metropolis", "permute_copy", "stratified", "multinomial", "inplace",
+                   "permute_copy_metropolis"):
         kernels = {}
         for counter in ("FETCH_SIZE", "WRITE_SIZE"):
             for name, kib in per_dispatch(family, counter).items():
@@ -587,9 +611,11 @@ def record_traffic(pmc_dir):
             continue
         total = sum(sum(v.values()) for v in kernels.values())
         rec[family] = {"bytes_per_launch": total, "kernels": kernels,
-                       "source_sha256": source_hash(family)}
+                       "source_sha256": source_hash(family),
+                       "bench_args": "--D 16" if family in ("inplace", "permute_copy_metropolis")
+                       else "--D 4"}
         log(f"traffic: {family} {total / 1e6:.2f} MB per call")
-    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
+    with open(path, "w") as f:
         json.dump(rec, f, indent=1)
         f.write("\n")
 
@@ -600,6 +626,8 @@ KERNEL_SOURCES = {
     "permute_copy": ["misc.hip", "common.h", "launch.h"],
     "stratified": ["prefix.hip", "prefix_impl.h", "prefix.h", "analysis.h", "common.h", "launch.h"],
     "multinomial": ["prefix.hip", "prefix_impl.h", "prefix.h", "analysis.h", "common.h", "launch.h"],
+    "inplace": ["inplace.hip", "prefix.h", "common.h", "launch.h"],
+    "permute_copy_metropolis": ["misc.hip", "common.h", "launch.h"],
 }
 
 
@@ -780,6 +808,60 @@ def dirichlet(torch, rs, workloads, args):
                 for k, v in point["resamplers"].items()),
                 file=sys.stderr, flush=True)
     return out
+
+
+def minimal_copy(torch, rs, workloads, P, B):
+    """The state update after Metropolis (random ancestors, eq. (5)'s B) at P,
+    D = 4 and 16, cold: the ancestor-indexed copy into a second buffer
+    against the in-place minimal-copy update (offspring form), with and
+    without the ancestors-to-offspring conversion. Algorithmic HBM bytes per
+    particle: copy 4 + 8D; in place 8D per hole + 8 (the counts read twice)
+    + 4 (a source tile's counts), the conversion 12 (ancestors read, counts
+    cleared and counted)."""
+    dev = torch.device("cuda", 0)
+    G = Graphs(torch)
+    res = {"note": "Metropolis ancestors at eq. (5)'s B; cold buffer sets (> 512 MiB per "
+                   "graph); per-call mean of graph replays"}
+    for D in (4, 16):
+        n_sets = max(4, -(-COLD_BYTES // (P * (8 * D + 12))))
+        sets = []
+        for k in range(n_sets):
+            lw = torch.from_numpy(workloads.normal_logweights(P, 1.0, 500 + k)).to(dev)
+            anc = rs.resample_metropolis(lw, B, 700 + k, 0)
+            off = rs.ancestors_to_offspring(anc)
+            x = torch.from_numpy(workloads.state_rows_normal(P, D, k)).to(dev)
+            sets.append({"anc": anc, "off": off, "off2": torch.empty_like(off), "x": x,
+                         "xo": torch.empty_like(x),
+                         "ws": torch.empty(int(rs.lib.rs_inplace_workspace_bytes(P)),
+                                           dtype=torch.uint8, device=dev)})
+            del lw
+        holes = float(np.mean([(bs["off"] == 0).float().mean().item() for bs in sets]))
+        forms = {
+            "permute_copy_us": lambda bs: rs.permute_copy(bs["anc"], bs["x"], x_out=bs["xo"]),
+            "inplace_us": lambda bs: rs.offspring_update_inplace(bs["off"], bs["x"], ws=bs["ws"]),
+            "anc_to_off_plus_inplace_us": lambda bs: (
+                rs.ancestors_to_offspring(bs["anc"], off=bs["off2"]),
+                rs.offspring_update_inplace(bs["off2"], bs["x"], ws=bs["ws"])),
+        }
+        out = {"holes_fraction": holes, "buffer_sets": n_sets}
+        for name, fn in forms.items():
+            g = G.capture(lambda fn=fn: [fn(bs) for bs in sets])
+            G.replay_ms([g], 2)
+            ms = G.replay_ms([g], 6)
+            out[name] = float(np.mean(ms)) / n_sets * 1e3
+            del g
+        alg_copy = 4 + 8 * D
+        alg_inplace = 8 * D * holes + 12
+        out["bytes_per_particle"] = {"permute_copy": alg_copy, "inplace": alg_inplace,
+                                     "anc_to_off_plus_inplace": alg_inplace + 12}
+        out["bytes_ratio_vs_permute_copy"] = alg_inplace / alg_copy
+        res[f"D{D}"] = out
+        log(f"minimal_copy D={D}: holes {holes:.3f}; copy {out['permute_copy_us']:.1f} us, "
+            f"in place {out['inplace_us']:.1f} us, with conversion "
+            f"{out['anc_to_off_plus_inplace_us']:.1f} us")
+        del sets
+        torch.cuda.empty_cache()
+    return res
 
 
 def batched(torch, rs, workloads, args):

@@ -243,6 +243,34 @@ int permute_copy(const int32_t *anc, const float *x_in, float *x_out, int64_t P,
                  int32_t *status, hipStream_t stream);
 
 /*
+ * Minimal-copy state update from offspring counts (Sec. 2 gives a
+ * resampler's output as offspring o_j, the number of copies of particle j,
+ * and notes that offspring and ancestors convert into each other). After
+ * resampling every particle carries weight 1 / P, so the new population is
+ * the multiset {x_j repeated o_j times} and slot order is free. This update
+ * rewrites x IN PLACE into that multiset moving only the rows that must
+ * change: row j stays in slot j whenever o_j >= 1, and each slot i with
+ * o_i = 0 (a hole) receives one extra copy (o_j - 1 of them for each j with
+ * o_j >= 2), the holes in increasing slot order paired with the extras in
+ * increasing order of j. HBM traffic is about 8D bytes per hole (plus 12 to
+ * 16 bytes per particle of counts and indices) instead of 4 + 8D per particle
+ * for permute_copy into a second buffer.
+ *   off    [device] int32[P]   offspring counts (as the stratified/systematic
+ *                              resamplers or ancestors_to_offspring write them)
+ *   x      [device] float[P x D] row-major state, updated in place; D >= 1
+ *   anc    [device] int32[P]   nullable; receives the particle whose row slot i
+ *                              holds afterwards (i itself where o_i >= 1)
+ *   ws     [device] workspace of ws_bytes >= rs_inplace_workspace_bytes(P)
+ *   status [device] int32[1]   nullable; RS_FLAG_BAD_ANCESTOR if a count is
+ *                              negative or the counts do not sum to P (then x
+ *                              is unchanged and anc is the identity)
+ * off, x, anc and ws must not overlap. Three launches; graph-capturable.
+ */
+size_t rs_inplace_workspace_bytes(int64_t P);
+int offspring_update_inplace(const int32_t *off, float *x, int64_t P, int32_t D, int32_t *anc,
+                             void *ws, size_t ws_bytes, int32_t *status, hipStream_t stream);
+
+/*
  * log sum_i exp(lw_i) in binary64 (the normalising constant of Sec. 1's
  * weighting step; a bootstrap filter adds it, minus log P, to its
  * log-likelihood each step). out [device] double[1].

@@ -116,6 +116,9 @@ def _load():
         "resample_batch": (ctypes.c_int, [ctypes.POINTER(BatchPlan), vp]),
         "rs_metropolis_get_tuning": (ctypes.c_int, [ctypes.POINTER(Tuning)]),
         "rs_prefix_set_path": (ctypes.c_int, [ctypes.c_int, i64]),
+        "rs_inplace_workspace_bytes": (sz, [i64]),
+        "offspring_update_inplace": (ctypes.c_int, [vp, vp, i64, ctypes.c_int32, vp, vp, sz,
+                                                    i32p, vp]),
         "rs_prefix_get_path": (ctypes.c_int, []),
     }
     for name, (res, args) in sig.items():

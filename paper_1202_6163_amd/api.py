@@ -242,6 +242,29 @@ def permute_copy(anc, x_in, x_out=None, status=None, stream=None):
     return x_out
 
 
+def offspring_update_inplace(off, x, anc=None, ws=None, status=None, stream=None):
+    """Minimal-copy update of the state rows x (P x D, in place) to o_j copies
+    of row j; returns (x, anc) with anc[i] the particle slot i holds."""
+    _need(off, torch.int32, "off")
+    _need(x, torch.float32, "x")
+    P = off.numel()
+    if P == 0:
+        return x, anc
+    if x.numel() % P:
+        raise ValueError("x must hold P rows")
+    D = x.numel() // P
+    if anc is not None:
+        _need(anc, torch.int32, "anc", P)
+    if ws is None:
+        ws = torch.empty(int(lib.rs_inplace_workspace_bytes(P)), dtype=torch.uint8,
+                         device=x.device)
+    _need(ws, torch.uint8, "ws")
+    check(lib.offspring_update_inplace(_ptr(off), _ptr(x), P, D, _ptr(anc), _ptr(ws), ws.numel(),
+                                       _status_ptr(status), _stream_handle(stream)),
+          "offspring_update_inplace")
+    return x, anc
+
+
 def rs_log_sum_exp(lw, out=None, ws=None, status=None, stream=None):
     _need(lw, torch.float32, "lw")
     P = lw.numel()

@@ -299,6 +299,26 @@ int permute_copy(const int32_t *anc, const float *x_in, float *x_out, int64_t P,
     return map_rc(rs::launch_permute_copy(anc, x_in, x_out, P, D, status, stream));
 }
 
+size_t rs_inplace_workspace_bytes(int64_t P)
+{
+    return P < 1 ? 0 : rs::inplace_workspace_bytes(P);
+}
+
+int offspring_update_inplace(const int32_t *off, float *x, int64_t P, int32_t D, int32_t *anc,
+                             void *ws, size_t ws_bytes, int32_t *status, hipStream_t stream)
+{
+    if (P == 0) return RS_OK;
+    if (!off || !x || !ws || misaligned(ws) || P < 0 || P > kMaxP || D < 1) return RS_EINVAL;
+    const size_t rows = (size_t)P * (size_t)D * sizeof(float), p4 = 4 * (size_t)P;
+    if (overlaps(off, p4, x, rows)) return RS_EINVAL;
+    if (anc && (overlaps(anc, p4, off, p4) || overlaps(anc, p4, x, rows))) return RS_EINVAL;
+    if (ws_bytes < rs_inplace_workspace_bytes(P)) return RS_EWORKSPACE;
+    if (overlaps(ws, ws_bytes, off, p4) || overlaps(ws, ws_bytes, x, rows) ||
+        (anc && overlaps(ws, ws_bytes, anc, p4)))
+        return RS_EINVAL;
+    return map_rc(rs::launch_offspring_update_inplace(off, x, P, D, anc, ws, status, stream));
+}
+
 int rs_log_sum_exp(const float *lw, int64_t P, double *out, void *ws, size_t ws_bytes,
                    int32_t *status, hipStream_t stream)
 {

@@ -96,6 +96,12 @@ int launch_permute_copy(const int32_t *anc, const float *x_in, float *x_out, int
 
 int launch_zero(void *ptr, size_t bytes, hipStream_t stream);
 
+// Minimal-copy state update from offspring counts (inplace.hip): workspace
+// bytes and the three launches.
+size_t inplace_workspace_bytes(int64_t P);
+int launch_offspring_update_inplace(const int32_t *off, float *x, int64_t P, int32_t D,
+                                    int32_t *anc, void *ws, int32_t *status, hipStream_t stream);
+
 int launch_gather_probe(const float *w, uint32_t n, uint32_t threads, uint32_t rounds,
                         uint32_t salt, float *out, hipStream_t stream);
 int launch_philox_probe(uint64_t seed, uint32_t threads, uint32_t rounds, uint32_t *out,

@@ -95,6 +95,45 @@ __global__ __launch_bounds__(kThreads) void copy_rows_vec4(const int32_t *__rest
     raise_flags(status, fl);
 }
 
+// Rows of COLS 16-byte vectors (D = 4 COLS, COLS = 2, 4 or 8): COLS
+// consecutive lanes share a row, one vector each, so every load instruction
+// reads whole rows; a row scattered by random ancestors is then fetched once
+// instead of once per vector. Each thread handles kRows (row, vector) pairs
+// spaced a grid apart, all loads in flight together.
+template <int COLS>
+__global__ __launch_bounds__(kThreads) void copy_rows_wide(const int32_t *__restrict__ anc,
+                                                           const float4 *__restrict__ x_in,
+                                                           float4 *__restrict__ x_out, int64_t P,
+                                                           int32_t *status)
+{
+    const int64_t nthreads = (int64_t)gridDim.x * kThreads, total = P * COLS;
+    int fl = 0;
+    for (int64_t e0 = (int64_t)blockIdx.x * kThreads + threadIdx.x; e0 < total;
+         e0 += kRows * nthreads) {
+        int32_t a[kRows];
+#pragma unroll
+        for (int k = 0; k < kRows; ++k) {
+            const int64_t e = e0 + k * nthreads;
+            a[k] = e < total ? anc[e / COLS] : 0;
+        }
+        float4 v[kRows];
+#pragma unroll
+        for (int k = 0; k < kRows; ++k) {
+            const int64_t e = e0 + k * nthreads;
+            const bool ok = a[k] >= 0 && (int64_t)a[k] < P;
+            v[k] = (e < total && ok) ? x_in[(int64_t)a[k] * COLS + (e % COLS)]
+                                     : make_float4(0.f, 0.f, 0.f, 0.f);
+            if (e < total && !ok) fl |= kFlagBadAncestor;
+        }
+#pragma unroll
+        for (int k = 0; k < kRows; ++k) {
+            const int64_t e = e0 + k * nthreads;
+            if (e < total) x_out[e] = v[k];
+        }
+    }
+    raise_flags(status, fl);
+}
+
 // D = 1: four rows per thread (one 16-byte ancestor load, four 4-byte
 // gathers, one 16-byte store).
 __global__ __launch_bounds__(kThreads) void copy_rows_d1(const int32_t *__restrict__ anc,
@@ -185,12 +224,26 @@ int launch_permute_copy(const int32_t *anc, const float *x_in, float *x_out, int
         hipLaunchKernelGGL(copy_rows_d1, dim3(grid_for((P + 3) / 4)), dim3(kThreads), 0, stream,
                            anc, x_in, x_out, P, status);
     } else if (vec_ok) {
-        int64_t grid = (P + kThreads * kRows - 1) / (kThreads * kRows);
+        const int cols = D / 4;
+        const bool wide = cols == 2 || cols == 4 || cols == 8;
+        const int64_t units = wide ? P * cols : P;  // (row, vector) pairs or rows
+        int64_t grid = (units + kThreads * kRows - 1) / (kThreads * kRows);
         if (grid < 1) grid = 1;
         if (grid > 65535) grid = 65535;
-        hipLaunchKernelGGL(copy_rows_vec4, dim3((uint32_t)grid), dim3(kThreads), 0, stream, anc,
-                           reinterpret_cast<const float4 *>(x_in),
-                           reinterpret_cast<float4 *>(x_out), P, D / 4, status);
+        const float4 *in4 = reinterpret_cast<const float4 *>(x_in);
+        float4 *out4 = reinterpret_cast<float4 *>(x_out);
+        if (cols == 2)
+            hipLaunchKernelGGL(copy_rows_wide<2>, dim3((uint32_t)grid), dim3(kThreads), 0, stream,
+                               anc, in4, out4, P, status);
+        else if (cols == 4)
+            hipLaunchKernelGGL(copy_rows_wide<4>, dim3((uint32_t)grid), dim3(kThreads), 0, stream,
+                               anc, in4, out4, P, status);
+        else if (cols == 8)
+            hipLaunchKernelGGL(copy_rows_wide<8>, dim3((uint32_t)grid), dim3(kThreads), 0, stream,
+                               anc, in4, out4, P, status);
+        else
+            hipLaunchKernelGGL(copy_rows_vec4, dim3((uint32_t)grid), dim3(kThreads), 0, stream,
+                               anc, in4, out4, P, cols, status);
     } else {
         hipLaunchKernelGGL(copy_rows_scalar, dim3(grid_for(P * (int64_t)D)), dim3(kThreads), 0,
                            stream, anc, x_in, x_out, P, D, status);

@@ -446,8 +446,8 @@ def test_offspring_bad_ancestor(rs):
 
 
 # every D up to 100003 particles; at the full size the D of the sweep (4) and D = 1
-COPY_CASES = [(P, D) for P in (1, 5, 1023, 4096, 100003) for D in (1, 3, 4, 8, 16)]
-COPY_CASES += [(1 << 20, 1), (1 << 20, 4)]
+COPY_CASES = [(P, D) for P in (1, 5, 1023, 4096, 100003) for D in (1, 3, 4, 8, 12, 16, 32)]
+COPY_CASES += [(1 << 20, 1), (1 << 20, 4), (1 << 20, 16)]
 
 
 @pytest.mark.parametrize("P,D", COPY_CASES)
@@ -461,8 +461,9 @@ def test_permute_copy_bit_exact(rs, P, D):
         assert np.array_equal(out.view(np.uint32), ref.view(np.uint32))
 
 
-def test_permute_copy_bad_ancestor_and_unaligned(rs):
-    P, D = 100, 4
+@pytest.mark.parametrize("D", [4, 16])
+def test_permute_copy_bad_ancestor_and_unaligned(rs, D):
+    P = 100
     x = workloads.state_rows_exact(P, D)
     anc = np.arange(P, dtype=np.int32)[::-1].copy()
     anc[7] = P
