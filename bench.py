@@ -320,6 +320,11 @@ def call_families(rs, ws, B_eq5, B_fixed):
         "systematic_and_copy": (fused("systematic"), 12, True),
         "multinomial_and_copy": (fused("multinomial"), 8, True),
         "metropolis_and_copy": (fused("metropolis"), 8, True),
+        # the one-launch form of the stratified resampler with the copy
+        # (rs_prefix_set_path; the path is read when a call is enqueued)
+        "stratified_and_copy_onepass": (lambda bs, k: (
+            rs.rs_prefix_set_path("onepass"), fused("stratified")(bs, k),
+            rs.rs_prefix_set_path("auto")), 12, True),
     }
 
 
@@ -399,6 +404,9 @@ def hbm_summary(per_call, P, D):
                                        form="resample_and_copy (copy in the fill)")
     out["systematic_and_copy"] = entry(per_call["systematic_and_copy"]["us"], 12 + 4 + 8 * D,
                                        form="resample_and_copy (copy in the fill)")
+    out["single_pass"] = entry(per_call["stratified_and_copy_onepass"]["us"], 12 + 4 + 8 * D,
+                               form="stratified resample_and_copy in one launch (tile sums "
+                                    "exchanged as tagged words; opt-in, slower)")
     out["note"] = ("bytes per particle as the method must move them: lw read twice, "
                    "ancestors written, (copy) ancestors read, rows read and written")
     return out
@@ -452,6 +460,7 @@ def headline(full, out_path):
                                           for k in ("value", "cores")}
         h["parity"] = cb["parity"]
     h["full_results"] = out_path
+    h = _round_floats(h)
     line = json.dumps(h)
     for drop in ("serving", "per_call_us", "crossover_sigma_by_P", "batched"):
         if len(line) <= 4000:
@@ -459,6 +468,17 @@ def headline(full, out_path):
         h.pop(drop, None)
         line = json.dumps(h)
     return h
+
+
+def _round_floats(v, sig=5):
+    """Floats to `sig` significant digits, recursively (keeps the line short)."""
+    if isinstance(v, float):
+        return float(f"{v:.{sig}g}") if math.isfinite(v) else v
+    if isinstance(v, dict):
+        return {k: _round_floats(x, sig) for k, x in v.items()}
+    if isinstance(v, (list, tuple)):
+        return [_round_floats(x, sig) for x in v]
+    return v
 
 
 def ceilings(torch, rs, G, lw, metro_iter_per_s):
@@ -995,16 +1015,20 @@ def serving(torch, args):
     1024) for the low-variance slots, stratified or systematic for the rest;
     weights and state uploaded from pinned host memory
     at admission, admitted by footprint, continuously batched on 4 streams.
-    Three load points: the configured 2000 req/s with P in [2^10, 2^20];
-    20000 req/s of smaller requests (P in [2^10, 2^14]) where batches of many
-    requests form; and that same load with every request in its own launches
-    (max_batch = 1)."""
+    Load points: the configured 2000 req/s with P in [2^10, 2^20]; then
+    smaller requests (P in [2^10, 2^14]) at 8000 and 16000 req/s, where
+    batches of many requests form, each also with every request in its own
+    launches (max_batch = 1): at 8000 req/s both keep up and the latencies
+    compare; at 16000 req/s the offered particles/s exceed what per-request
+    launches sustain."""
     from paper_1202_6163_amd.serve import GpuExecutor, Payloads, make_requests, serve, summarize
     pay = Payloads(1 << 20)
     heavy_s = min(3.0, args.serve_seconds)
     points = (("config_load", 2000.0, args.serve_seconds, 20, 32 << 30, 256),
-              ("many_small", 20000.0, heavy_s, 14, 1 << 30, 256),
-              ("many_small_per_request_launches", 20000.0, heavy_s, 14, 1 << 30, 1))
+              ("small_8k", 8000.0, heavy_s, 14, 1 << 30, 256),
+              ("small_8k_per_request_launches", 8000.0, heavy_s, 14, 1 << 30, 1),
+              ("small_16k", 16000.0, heavy_s, 14, 1 << 30, 256),
+              ("small_16k_per_request_launches", 16000.0, heavy_s, 14, 1 << 30, 1))
     out = {"note": "latency = server-observed completion - arrival on one host clock; "
                    "includes the host-to-device upload of weights and state"}
     for name, rate, secs, p_hi, budget, max_batch in points:

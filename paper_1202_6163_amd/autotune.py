@@ -1,8 +1,11 @@
 """Autotuner for the launch parameters (they change speed, never results).
 
 Metropolis single calls: threads per block, iterations per round (unroll),
-the LDS staging threshold and lanes per chain, chosen to minimise the summed
-time over a set of (P, B) points. Batched launches: chains per work item,
+the LDS staging threshold and lanes per chain, chosen to minimise the mean
+slowdown over a set of (P, B) points (the geometric mean of each point's
+time over the best time any candidate reached there, so a 4096-particle
+point where LDS staging decides counts as much as a 2^20 point that takes a
+thousand times longer). Batched launches: chains per work item,
 unroll, LDS staging threshold and persistent grid size, chosen on a batch
 shaped like the target workload. Results are stored in tuning.json next to
 this file, keyed by device name and library version, and applied when the
@@ -60,8 +63,11 @@ def tune_metropolis(torch, rs, points, candidates, reps=5):
             total += ms
         results.append((total, cand, per))
         print(f"metropolis {cand}: {total:.3f} ms", file=sys.stderr, flush=True)
-    results.sort(key=lambda r: r[0])
-    return results
+    best = {k: min(r[2][k] for r in results) for k in results[0][2]}
+    scored = [(float(np.exp(np.mean([np.log(per[k] / best[k]) for k in per]))), cand, per)
+              for _, cand, per in results]
+    scored.sort(key=lambda r: r[0])
+    return scored
 
 
 def tune_batch(torch, rs, instances, candidates, reps=5):
@@ -130,12 +136,19 @@ def main():
         rec = json.load(open(args.out))
     except (OSError, ValueError):
         rec = {}
+    # the staging threshold's effect: the best candidate with each threshold,
+    # per point (P <= 16384 can be staged; 40960 also stages 2^15-2^16 points
+    # if they fit, which they do not at the points used here)
+    by_lds = {}
+    for t, c, per in mres:
+        by_lds.setdefault(str(c["lds_max_p"]), {"slowdown": t, **c, "ms_per_point": per})
     rec[key] = {
         "metropolis": best_m, "batch": best_b,
         "metropolis_points": [list(p) for p in points],
-        "metropolis_top": [dict(ms=float(t), **c) for t, c, _ in mres[:5]],
-        "metropolis_default_ms": float(next(t for t, c, _ in mres if c == dict(
-            block=256, unroll=8, lds_max_p=16384, lanes_per_chain=0))),
+        "metropolis_objective": "geometric mean over points of time / best time at the point",
+        "metropolis_top": [dict(slowdown=float(t), **c, ms_per_point=per)
+                           for t, c, per in mres[:5]],
+        "metropolis_best_per_lds_threshold": by_lds,
         "batch_top": [dict(ms=float(t), **c) for t, c in bres[:5]],
     }
     with open(args.out, "w") as f:

@@ -118,15 +118,19 @@ int launch_variant(const float *lw, int32_t *anc, uint32_t P, uint32_t B, uint64
     return launch_status();
 }
 
-// Lanes per chain when not fixed by the tuning: enough lanes to fill the
-// chip (about 2^17), no more than the iterations can use.
+// Lanes per chain when not fixed by the tuning: up to 2^16 threads in all,
+// no more lanes than the iterations can use, and never two (measured at
+// unroll 4, block 256: a two-lane group was slower than both one lane and
+// four at every P from 4096 to 262144; past 2^16 threads the extra lanes
+// only add group shuffles, e.g. P = 65536, B = 64: 20.0 us with one lane,
+// 27.0 with two, 28.4 with four).
 int auto_lanes_log2(uint32_t P, uint32_t B, int unroll)
 {
-    const uint64_t target = 1u << 17;
+    const uint64_t target = 1u << 16;
     int lg = 0;
     while (lg < 6 && ((uint64_t)P << (lg + 1)) <= target && ((uint64_t)unroll << (lg + 1)) <= B)
         ++lg;
-    return lg;
+    return lg == 1 ? 0 : lg;
 }
 
 // Both logs of every point of the u grid (m = 0 .. 2^23 - 1, u = (2m+1) 2^-24).
