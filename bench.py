@@ -24,7 +24,8 @@ gpurun_out/bench_full.json):
   step_fixed_B  the same step with Metropolis at a fixed B (flagged when B
                 is below eq. (5)'s);
   roofline      the dominant kernel of the step against its ceiling;
-  roofline_hbm  the stratified resample + state copy path against HBM;
+  roofline_hbm  the stratified resample + state copy path against HBM (also
+                in the one-launch form, and at 2^22 and 2^24);
   sweep         per sigma and P, p50/p99 particles/s of every resampler
                 (Metropolis at each B), with and without the copy, the
                 accuracy metric sum_i (o_i/P - w_i/W)^2, the ESS, eq. (5)'s B
@@ -34,11 +35,14 @@ gpurun_out/bench_full.json):
                 sorted-weight variants;
   batched       1024 independent instances in one batched launch against
                 per-instance calls;
+  minimal_copy  the state update after Metropolis: the ancestor-indexed copy
+                against the in-place minimal-copy update (D = 4 and 16);
   filter        the bootstrap filter (P = 2^18, D = 8, T = 200) against the
                 Kalman log-likelihood;
   pmcmc         particle marginal Metropolis-Hastings with batched filters;
-  serving       Poisson arrivals at 2000 req/s (and a heavier load point):
-                latency percentiles;
+  serving       Poisson arrivals at 2000 req/s, and small requests at 8000
+                and 16000 req/s batched and with per-request launches:
+                latency percentiles and particles/s;
   cpu_baseline  the CPU oracle on a bounded sample of the same step (one
                 pinned core, and all cores), with the GPU's outputs on the
                 same inputs compared against it.
