@@ -927,7 +927,29 @@ def batched(torch, rs, workloads, args):
     torch.cuda.synchronize()
     eager_ms = (time.perf_counter() - t0) * 1e3
     tb, tp = pct(ms_b, 50), pct(ms_p, 50)
+    # the two halves on their own: the Metropolis instances against the L2
+    # request rate (one proposal gather per iteration), the stratified ones
+    # against HBM (lw twice, ancestors, the D = 16 copy: 12 + 4 + 128 B)
+    halves = {}
+    for kind in ("metropolis", "stratified"):
+        sub = [d for d in insts if d["kind"] == kind]
+        bk = Batch(sub)
+        gk = G.capture(bk.run)
+        msk = pct(G.replay_ms([gk], 10), 50)
+        n_k = sum(int(d["lw"].numel()) for d in sub)
+        h = {"instances": len(sub), "particles": n_k, "ms_p50": msk}
+        if kind == "metropolis":
+            it = n_k * 64
+            h.update(iterations=it, iterations_per_s=it / (msk * 1e-3),
+                     frac_of_l2_request_peak=it / (msk * 1e-3) / (L2_PEAK_GREQ_S * 1e9))
+        else:
+            by = n_k * (12 + 4 + 8 * 16)
+            h.update(bytes=by, GB_per_s=by / (msk * 1e-3) / 1e9,
+                     frac_of_hbm_peak=by / (msk * 1e-3) / 1e9 / HBM_PEAK_GBS)
+        halves[kind] = h
+        del gk, bk
     return {"instances": len(P), "particles": total, "D": 16,
+            "halves": halves,
             "batched_ms_p50": tb, "batched_ms_p99": pct(ms_b, 99),
             "per_instance_graph_ms_p50": tp, "per_instance_eager_ms": eager_ms,
             "batched_instances_per_s": len(P) / (tb * 1e-3),

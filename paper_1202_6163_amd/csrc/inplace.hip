@@ -292,20 +292,23 @@ __global__ __launch_bounds__(kIpThreads) void ip_move_kernel(const int32_t *__re
         for (int64_t e = tid; e < (int64_t)ht * cols; e += kIpThreads) {
             const int64_t q = e / cols, c = e - q * cols;
             const int32_t src = sh_src[q];
-            if (src < 0) continue;
+            if (src < 0) {  // a hole left without a source: a library bug
+                fl |= kFlagInternal;
+                continue;
+            }
             x4[(int64_t)sh_hole[q] * cols + c] = x4[(int64_t)src * cols + c];
         }
     } else {
         for (int64_t e = tid; e < (int64_t)ht * D; e += kIpThreads) {
             const int64_t q = e / D, d = e - q * D;
             const int32_t src = sh_src[q];
-            if (src < 0) continue;
+            if (src < 0) {
+                fl |= kFlagInternal;
+                continue;
+            }
             x[(int64_t)sh_hole[q] * D + d] = x[(int64_t)src * D + d];
         }
     }
-    if (tid == 0)
-        for (int q = 0; q < ht; ++q)
-            if (sh_src[q] < 0) fl |= kFlagInternal;
     raise_flags(status, fl);
 }
 
