@@ -709,8 +709,11 @@ def sweep(torch, rs, workloads, args):
                      "B_eq5_eps1e-2": rs.metropolis_B(P, wmax, 1e-2),
                      "B_eq5_eps1e-3": rs.metropolis_B(P, wmax, 1e-3), "resamplers": {}}
 
-            def measure(call, with_copy):
-                R = max(1, min(64, int(2e5 // P) + 1))  # calls per graph (>= ~50 us of work)
+            def measure(call, with_copy, r_min=1):
+                # calls per graph: about 2e5 particles of work, and at least
+                # r_min (4 for the short prefix calls, so a replay's own launch
+                # cost is spread over several calls at every P)
+                R = max(r_min, min(64, int(2e5 // P) + 1))
 
                 def body():
                     for k in range(R):
@@ -739,8 +742,9 @@ def sweep(torch, rs, workloads, args):
                 calls[f"metropolis_B{Bm}"] = (
                     lambda k, Bm=Bm: rs.resample_metropolis(lw, Bm, k, 0, anc=anc))
             for name, call in calls.items():
-                r = measure(call, False)
-                r["with_copy"] = measure(call, True)
+                r_min = 1 if name.startswith("metropolis") else 4
+                r = measure(call, False, r_min)
+                r["with_copy"] = measure(call, True, r_min)
                 r["error"] = accuracy(call)
                 point["resamplers"][name] = r
             strat = point["resamplers"]["stratified"]["p99_pps"]
