@@ -774,16 +774,15 @@ def dirichlet(torch, rs, workloads, args):
     alpha in {10, 1, .1, .01}; accuracy metric sum (o/P - w/W)^2 averaged over
     R resamplings and per-call time for multinomial, stratified, systematic,
     Metropolis at eq. (5)'s B (eps = 0.01, capped at 4096) and the
-    sorted-weight multinomial and systematic. Per-call times are eager calls
-    (events around R back-to-back calls, host dispatch included) for every
-    resampler, since the sort inside the sorted variants is not
-    graph-capturable; the others also get the GPU time of a graph of R calls."""
+    sorted-weight multinomial and systematic. Per-call times: eager calls
+    (events around R back-to-back calls, host dispatch included) and the GPU
+    time of a graph of R calls, for every resampler."""
     dev = torch.device("cuda", 0)
     R = args.dirichlet_R
     G = Graphs(torch)
     out = {"note": "us_per_call: eager per-call time (host dispatch included); "
-                   "us_per_call_graph: GPU time per call in a graph of R calls (not for the "
-                   "sorted variants); error averaged over R resamplings with different seeds",
+                   "us_per_call_graph: GPU time per call in a graph of R calls; error averaged "
+                   "over R resamplings with different seeds",
            "R": R, "points": []}
     for P in (256, 1024, 4096, 16384, 65536):
         anc = torch.empty(P, dtype=torch.int32, device=dev)
@@ -826,10 +825,9 @@ def dirichlet(torch, rs, workloads, args):
                 e1.record()
                 torch.cuda.synchronize()
                 point["resamplers"][name] = {"error": err, "us_per_call": e0.elapsed_time(e1) * 1e3 / R}
-                if not name.endswith("_sorted"):
-                    g = G.capture(lambda call=call: [call(900 + k) for k in range(R)])
-                    ms = G.replay_ms([g], 3)
-                    point["resamplers"][name]["us_per_call_graph"] = pct(ms, 50) * 1e3 / R
+                g = G.capture(lambda call=call: [call(900 + k) for k in range(R)])
+                ms = G.replay_ms([g], 3)
+                point["resamplers"][name]["us_per_call_graph"] = pct(ms, 50) * 1e3 / R
             out["points"].append(point)
             print(f"dirichlet P={P} alpha={alpha}: " + ", ".join(
                 f"{k} {v['us_per_call']:.1f}us ({v.get('us_per_call_graph', float('nan')):.1f} in a graph)"

@@ -211,14 +211,14 @@ int resample_and_copy(int kind, const float *lw, int32_t *anc, int32_t *off, int
  * decreasing log-weight, equal weights by index (-0 counts as +0); the
  * resampler `kind` (RS_STRATIFIED, RS_SYSTEMATIC or RS_MULTINOMIAL) runs on
  * the weights in that order with the given seed and instance; anc receives
- * the chosen particles' original indices. The sort is rocPRIM's stable
- * descending radix sort; its library internals may issue memory fills, so
- * this call is not meant for graph capture.
+ * the chosen particles' original indices. The sort is the library's own
+ * stable radix sort (four 8-bit passes of histogram, scan and scatter
+ * launches); the call allocates nothing and issues no memory fills, so it
+ * can be captured in a graph.
  *   lw, anc  [device] float[P] / int32[P], not overlapping
  *   ws       [device] workspace of ws_bytes >= rs_sorted_workspace_bytes(P, kind)
  *   status   [device] int32[1], nullable; flagged inputs give identity ancestors
- * Errors: RS_EINVAL, RS_EWORKSPACE (also if the sort needs more scratch than
- * the workspace bound), RS_EHIP.
+ * Errors: RS_EINVAL, RS_EWORKSPACE, RS_EHIP.
  */
 size_t rs_sorted_workspace_bytes(int64_t P, int kind);
 int resample_sorted(int kind, const float *lw, int32_t *anc, int64_t P, uint64_t seed,

@@ -199,7 +199,7 @@ def rs_workspace_log_sum_exp(ws, P, out=None, stream=None):
 def resample_sorted(kind, lw, seed, instance=0, anc=None, ws=None, status=None, stream=None):
     """Sorted-weight variant of resampler `kind` ("stratified", "systematic",
     "multinomial" or the RS code); returns the ancestors (original indices).
-    Not for graph capture (see include/resample.h)."""
+    Graph-capturable when ws is given."""
     code = {"stratified": STRATIFIED, "systematic": SYSTEMATIC,
             "multinomial": MULTINOMIAL}.get(kind, kind)
     _need(lw, torch.float32, "lw")

@@ -275,8 +275,7 @@ int resample_sorted(int kind, const float *lw, int32_t *anc, int64_t P, uint64_t
     if (overlaps(lw, 4 * p, anc, 4 * p)) return RS_EINVAL;
     if (ws_bytes < rs_sorted_workspace_bytes(P, kind)) return RS_EWORKSPACE;
     if (overlaps(ws, ws_bytes, lw, 4 * p) || overlaps(ws, ws_bytes, anc, 4 * p)) return RS_EINVAL;
-    const int rc = rs::launch_sorted(kind, lw, anc, P, seed, instance, ws, status, stream);
-    return rc == -2 ? RS_EWORKSPACE : map_rc(rc);
+    return map_rc(rs::launch_sorted(kind, lw, anc, P, seed, instance, ws, status, stream));
 }
 
 int ancestors_to_offspring(const int32_t *anc, int32_t *off, int64_t P, int32_t *status,

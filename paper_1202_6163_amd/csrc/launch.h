@@ -73,8 +73,8 @@ int launch_log_sum_exp(const float *lw, int64_t P, double *out, void *ws, int32_
                        hipStream_t stream);
 int launch_workspace_lse(const void *ws, int64_t P, double *out, hipStream_t stream);
 
-// Sorted-weight variant: workspace sections (byte offsets) and the launcher.
-// Returns 0, -2 (workspace too small for the sort) or -3.
+// Sorted-weight variant: workspace sections (byte offsets) and the launcher
+// (the radix sort's histograms live in the temp section). Returns 0 or -3.
 struct SortedLayout {
     size_t prefix, keys_in, keys_out, idx_in, perm, a_sorted, temp, temp_bytes, total;
 };

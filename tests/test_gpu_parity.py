@@ -509,7 +509,7 @@ def test_measurement_probes_run(rs):
 
 # ----------------------------------------------------------------- sorted-weight variants
 @pytest.mark.parametrize("kind", PREFIX)
-@pytest.mark.parametrize("P", [1, 5, 1000, 5000, 100003, 1 << 16])
+@pytest.mark.parametrize("P", [1, 5, 1000, 4096, 4097, 5000, 100003, 1 << 16, (1 << 20) + 3])
 def test_sorted_variant_parity(rs, kind, P):
     seed, inst = P % 13 + 2, 1
     lw = workloads.normal_logweights(P, 1.5, seed)
@@ -543,6 +543,32 @@ def test_sorted_variant_ties_and_flags(rs, kind):
     st = torch.zeros(1, dtype=torch.int32, device="cuda")
     anc = host(rs.resample_sorted(kind, dev(bad), 1, 0, status=st))
     assert int(host(st)[0]) == rs.FLAG_NAN and np.array_equal(anc, np.arange(2000))
+
+
+@pytest.mark.parametrize("kind", PREFIX)
+def test_sorted_variant_graph_replays(rs, kind):
+    """The library's own radix sort issues no memory fills: the sorted
+    variant captured in a graph repeats the eager result on every replay,
+    with eager work on the same workspace in between."""
+    P = 300007
+    lw = dev(workloads.normal_logweights(P, 2.0, 41))
+    ws = torch.empty(int(rs.lib.rs_sorted_workspace_bytes(P, rs.MULTINOMIAL)), dtype=torch.uint8,
+                     device="cuda")
+    want = host(rs.resample_sorted(kind, lw, 7, 2, ws=ws))
+    anc = torch.empty(P, dtype=torch.int32, device="cuda")
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        rs.resample_sorted(kind, lw, 7, 2, anc=anc, ws=ws)
+    other = dev(workloads.normal_logweights(P, 1.0, 42))
+    for k in range(4):
+        anc.fill_(-1)
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(anc), want), f"replay {k}"
+        rs.resample_sorted(kind, other, k, 0, ws=ws)
+        torch.cuda.synchronize()
 
 
 # ----------------------------------------------------------------- fused resample + copy
