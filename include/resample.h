@@ -473,9 +473,9 @@ int rs_metropolis_get_tuning(rs_metropolis_tuning *t);       /* t [host] */
  * results are the same bits in every form). Sec. 2 notes that the prefix sum
  * needs thread communication and several kernel launches, and Sec. 3 that
  * launch overhead dominated at small sizes; up to P = 2^20 these calls can
- * run as ONE launch in which the blocks exchange their tile sums through
- * device memory (tagged words, no fence) instead of through kernel
- * boundaries.
+ * run as ONE resampling launch in which the blocks exchange their tile sums
+ * through device memory (tagged words, no fence) instead of through kernel
+ * boundaries, after a small fill kernel that clears those words.
  *   path    RS_PATH_AUTO (the faster form as measured on the MI355X: the
  *           launches at every size so far), RS_PATH_LAUNCHES (always the tile
  *           reduction, table and fill launches) or RS_PATH_ONEPASS (the one

@@ -53,9 +53,10 @@ int launch_metropolis_adaptive(const float *lw, int32_t *anc, int64_t P, double 
 
 // Which form the stratified/systematic single calls take: kPathAuto (the
 // faster one: the launches), kPathLaunches (always the tile reduction, table
-// and fill launches) or kPathOnePass (the one launch wherever it applies). wait_ns bounds a one-pass block's wait for the
-// others' tile values before it reduces the missing tiles itself (< 0: the
-// default). Process-wide; returns 0 or -1 (unknown path).
+// and fill launches) or kPathOnePass (the clearing fill and the one
+// resampling launch wherever it applies). wait_ns bounds a one-pass block's
+// wait for the others' tile values before it reduces the missing tiles
+// itself (< 0: the default). Process-wide; returns 0 or -1 (unknown path).
 constexpr int kPathAuto = 0, kPathLaunches = 1, kPathOnePass = 2;
 int set_prefix_path(int path, int64_t wait_ns);
 int get_prefix_path();

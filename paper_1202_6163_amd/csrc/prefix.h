@@ -15,9 +15,10 @@
 // Up to kOnePassMaxTiles tiles the stratified/systematic resampler can also
 // run as one launch (onepass_kernel in prefix.hip): every block publishes its
 // tiles' (max, sum, flags) as tagged 64-bit words in the `pub` section and
-// reads all of them back; the tags come from a call counter in the `epoch`
-// section, so stale or uninitialised words are never taken for current ones
-// and this path, too, needs no initialisation.
+// reads all of them back. The launcher clears those words with a fill kernel
+// just before, and a published word is never zero, so words left by earlier
+// calls (of any kind or size) are never taken for current ones and this path,
+// too, needs no initialisation.
 #pragma once
 
 #include <stddef.h>
@@ -48,7 +49,7 @@ struct alignas(64) WsHeader {
 };
 
 struct WsLayout {
-    size_t header, tile_max, tile_sum, tile_flags, bound, count, win, epoch, pub, sub, guide, part,
+    size_t header, tile_max, tile_sum, tile_flags, bound, count, win, pub, sub, guide, part,
         cumw, total;
 };
 
@@ -100,9 +101,8 @@ __host__ __device__ inline WsLayout ws_layout(int64_t P, bool with_cumw)
     L.bound = L.tile_flags + ws_align(n * sizeof(int32_t));
     L.count = L.bound + ws_align(n * sizeof(double));
     L.win = L.count + ws_align(n * sizeof(int32_t));
-    // one-pass path: the call counter, then three tagged words per tile
-    L.epoch = L.win + ws_align((size_t)num_windows(P) * sizeof(int32_t));
-    L.pub = L.epoch + ws_align(sizeof(uint64_t));
+    // one-pass path: three tagged words per tile
+    L.pub = L.win + ws_align((size_t)num_windows(P) * sizeof(int32_t));
     // the multinomial sections (group ends, guide, draw parts, C) sit past the shared
     // ones at the same offsets whatever the kind; only the size differs
     L.sub = L.pub + ws_align(n * 3 * sizeof(uint64_t));

@@ -149,9 +149,10 @@ int launch_fill(const float *lw, int32_t *anc, int32_t *off, int64_t P, uint64_t
 }
 
 // ------------------------------------------------------ one-pass fill
-// Stratified/systematic resampling in one launch (P <= 2^20): the three
-// phases of the launches above (tile reduction, boundaries and counts, fill)
-// with the grid-wide step done inside the kernel. Block b owns tiles b and
+// Stratified/systematic resampling in one launch (P <= 2^20; the launcher
+// enqueues a small fill kernel before it): the three phases of the launches
+// above (tile reduction, boundaries and counts, fill) with the grid-wide step
+// done inside the kernel. Block b owns tiles b and
 // b + G (G = gridDim.x = ceil(n / 2)). It loads their log-weights (and, with
 // DS > 0, their state rows) once, reduces each tile exactly as
 // tile_reduce_body does and publishes (max, sum, flags) as three 64-bit words
@@ -163,28 +164,18 @@ int launch_fill(const float *lw, int32_t *anc, int32_t *off, int64_t P, uint64_t
 //
 // No release fence is needed: each word is self-contained, written and read
 // with relaxed device-scope atomics, which go to the point of coherence
-// shared by the eight XCDs (no L2 write-back). A word counts only when its tag
-// equals pub_tag(e, t, k), e being this call's value of the workspace's call
-// counter: words of earlier calls (smaller e) and uninitialised memory fail
-// that test except with probability 2^-32 per word (2^-96 for a tile's three).
-// Every block raises the counter past e once it holds all the values; before
-// that every block has read e (it published after reading it), so the next
-// call, ordered after this one, sees a larger value. The wait is bounded: a
-// block that has not seen a tile's words after wait_ticks of the real-time
-// clock reduces that tile itself (the same function, the same bits), so the
-// results never depend on all blocks being resident at once; only the speed
-// does.
-__device__ __forceinline__ uint32_t pub_tag(uint64_t e, int64_t t, int k)
+// shared by the eight XCDs (no L2 write-back). The launcher clears the 3n
+// words with a fill kernel ordered before this one, and a published word's
+// high half, pub_tag(t, k), is never zero: every word that passes the test
+// was written by this call, whatever earlier calls (of any kind or size)
+// left in the workspace, and replays of a captured graph clear them again.
+// The wait is bounded: a block that has not seen a tile's words after
+// wait_ticks of the real-time clock reduces that tile itself (the same
+// function, the same bits), so the results never depend on all blocks being
+// resident at once; only the speed does.
+__device__ __forceinline__ uint32_t pub_tag(int64_t t, int k)
 {
-    // a 32-bit integer hash (lowbias32 finaliser) of (call, tile, word)
-    uint32_t h = (uint32_t)e ^ ((uint32_t)(e >> 32) * 0x85EBCA6Bu) ^
-                 (((uint32_t)t * 4u + (uint32_t)k) * 0x9E3779B9u);
-    h ^= h >> 16;
-    h *= 0x7FEB352Du;
-    h ^= h >> 15;
-    h *= 0x846CA68Bu;
-    h ^= h >> 16;
-    return h;
+    return (uint32_t)(3 * t + k) + 1u;  // the word's index plus one (3n < 2^32)
 }
 
 // Word 0 of a tile: its max as binary32 bits, or, when the tile holds a NaN
@@ -217,7 +208,6 @@ __global__ __launch_bounds__(kTileThreads) void onepass_kernel(
     static_assert(kOnePassMaxTiles * (sizeof(int32_t) + 1) <= kChunk * sizeof(int32_t),
                   "the missing-tile list and bytes fit in sh_anc");
     __shared__ int32_t sh_anc[kChunk];
-    __shared__ uint64_t sh_epoch;
     __shared__ int64_t sh_cnt[2 * kOnePassTiles];        // lo, hi of the block's tiles
     __shared__ int64_t sh_win[kOnePassWindows][3];       // owner tile (-1: none), lo, hi
     __shared__ int sh_nmiss;
@@ -227,12 +217,10 @@ __global__ __launch_bounds__(kTileThreads) void onepass_kernel(
 
     const WsView ws = ws_view(ws_raw, P);
     const WsLayout L = ws_layout(P, false);
-    uint64_t *epoch = reinterpret_cast<uint64_t *>(ws_raw + L.epoch);
     uint64_t *pub = reinterpret_cast<uint64_t *>(ws_raw + L.pub);
     const int64_t n = num_tiles(P), G = gridDim.x, b = blockIdx.x;
     const int tid = threadIdx.x;
 
-    if (tid == 0) sh_epoch = __hip_atomic_load(epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     // every load of the block's own data is issued before the first wait
     float v[kOnePassTiles][4];
 #pragma unroll
@@ -275,14 +263,13 @@ __global__ __launch_bounds__(kTileThreads) void onepass_kernel(
         int fl;
         tile_reduce_vals(v[r], &mx, &s, &fl);
         if (tid == 0) {
-            const uint64_t e = sh_epoch;
             const uint64_t sb = (uint64_t)__double_as_longlong(s);
             uint64_t *w = pub + 3 * t;
-            __hip_atomic_store(w + 0, ((uint64_t)pub_tag(e, t, 0) << 32) | pub_max_word(mx, fl),
+            __hip_atomic_store(w + 0, ((uint64_t)pub_tag(t, 0) << 32) | pub_max_word(mx, fl),
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(w + 1, ((uint64_t)pub_tag(e, t, 1) << 32) | (sb >> 32),
+            __hip_atomic_store(w + 1, ((uint64_t)pub_tag(t, 1) << 32) | (sb >> 32),
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(w + 2, ((uint64_t)pub_tag(e, t, 2) << 32) | (sb & 0xFFFFFFFFu),
+            __hip_atomic_store(w + 2, ((uint64_t)pub_tag(t, 2) << 32) | (sb & 0xFFFFFFFFu),
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
@@ -301,7 +288,6 @@ __global__ __launch_bounds__(kTileThreads) void onepass_kernel(
     constexpr int kPolls = 3 * kOnePassMaxTiles / kTileThreads;  // words per thread at most
     static_assert(kPolls <= 32, "one mask bit per word");
     uint32_t *pay = reinterpret_cast<uint32_t *>(lds_cb);  // 3n payloads
-    const uint64_t e = sh_epoch;  // read after the reductions' barriers
     const int64_t nw = 3 * n;
     uint32_t need = 0, tag[kPolls];
 #pragma unroll
@@ -310,7 +296,7 @@ __global__ __launch_bounds__(kTileThreads) void onepass_kernel(
         tag[i] = 0;
         if (w < nw) {
             need |= 1u << i;
-            tag[i] = pub_tag(e, w / 3, (int)(w % 3));
+            tag[i] = pub_tag(w / 3, (int)(w % 3));
         }
     }
     const uint64_t start = wall_clock64();
@@ -390,9 +376,6 @@ __global__ __launch_bounds__(kTileThreads) void onepass_kernel(
         m = fmaxf(m, mt[k]);
     }
     __syncthreads();  // sh_bound (part of the payload space) is written below
-    // every block read e before publishing, so the counter may move on now
-    if (tid == 0)
-        __hip_atomic_fetch_max(epoch, e + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const TableSums sums = boundaries_tail(ws, n, t0, t1, true, fl, m, mt, S, sh_bound);
     if (b == 0 && tid == 0) {
         WsHeader *h = ws.h;
@@ -1133,6 +1116,10 @@ int try_onepass(const float *lw, int32_t *anc, int32_t *off, int64_t P, uint64_t
     const int64_t wait_ns = g_onepass_wait_ns.load() < 0 ? kOnePassWaitNs : g_onepass_wait_ns.load();
     const uint64_t ticks = (uint64_t)(wait_ns * ticks_per_ms / 1000000);
     if (smem && allow_dynamic_lds(fn, smem)) return -3;
+    // the published words start at zero, which no published word equals
+    if (const int rc = launch_zero(w + ws_layout(P, false).pub, (size_t)n * 3 * sizeof(uint64_t),
+                                   stream))
+        return rc;
     const dim3 grid((uint32_t)G), tb(kTileThreads);
     switch (DS) {
     case 0:

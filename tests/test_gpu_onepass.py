@@ -2,7 +2,8 @@
 form and against the oracle.
 
 The one-pass kernel exchanges the tile sums between blocks through tagged
-words in the workspace instead of kernel boundaries. Bar: ancestors,
+words in the workspace (cleared by a fill kernel before each call) instead of
+kernel boundaries. Bar: ancestors,
 offspring, cumulative weights, rows and the status word are bit for bit
 those of the three launches (same tile values, same boundary code, same
 fill), on every size up to 2^20 with ragged tails, with heavy tiles
@@ -123,8 +124,12 @@ def test_onepass_without_waiting(rs, path, kind, P):
 
 @pytest.mark.parametrize("fill", [0x00, 0xFF, "random", "stale"])
 def test_onepass_garbage_workspace(rs, path, fill):
-    """The tags keep words of earlier calls and uninitialised bytes out,
-    whatever the workspace holds before the call."""
+    """Whatever the workspace holds before the call, only this call's words
+    are taken. The first call never waits (wait bound 0), so every block takes
+    whatever valid-looking words it finds on its first read: the words an
+    earlier call on other weights left behind carry the same tags (a word's
+    tag is its index), and only the clearing fill before each call keeps
+    them out."""
     P = (1 << 20) - 5
     lw = torch.from_numpy(workloads.normal_logweights(P, 1.0, 14)).cuda()
     ref = run(rs, "launches", "stratified", lw, 9, 0)
@@ -133,7 +138,7 @@ def test_onepass_garbage_workspace(rs, path, fill):
         g = torch.Generator().manual_seed(3)
         ws.copy_(torch.randint(0, 256, (ws.numel(),), dtype=torch.uint8, generator=g).cuda())
     elif fill == "stale":
-        # the words an earlier call on other weights left behind, the counter unchanged
+        # the words an earlier call on other weights left behind
         other = torch.from_numpy(workloads.normal_logweights(P, 1.0, 15)).cuda()
         run(rs, "onepass", "stratified", other, 9, 0, ws=ws)
         snap = ws.clone()
@@ -143,13 +148,15 @@ def test_onepass_garbage_workspace(rs, path, fill):
         ws.fill_(fill)
     torch.cuda.synchronize()
     for k in range(3):
-        got = run(rs, "onepass", "stratified", lw, 9, 0, ws=ws)
+        got = run(rs, "onepass", "stratified", lw, 9, 0, ws=ws, wait_ns=0 if k == 0 else -1)
         same(ref, got, f"fill {fill} call {k}")
 
 
 def test_onepass_sizes_change_on_one_workspace(rs, path):
-    """Calls of growing and shrinking P share one workspace: the tiles a
-    smaller call did not publish still carry tags of older calls."""
+    """Calls of growing and shrinking P share one workspace, which earlier
+    tests may have used for any kind of call: the words a larger call
+    published, with the same tags, sit past and inside a smaller call's
+    words until the clearing fill."""
     sizes = [1 << 20, 3000, 1 << 20, 4097, 700000, 1 << 20, 1]
     ws = rs.workspace(1 << 20, rs.STRATIFIED, torch.device("cuda"))
     for k, P in enumerate(sizes):
@@ -161,9 +168,9 @@ def test_onepass_sizes_change_on_one_workspace(rs, path):
 
 
 def test_onepass_graph_replays(rs, path):
-    """A captured one-pass call replayed many times (the call counter lives in
-    device memory, so each replay is a new call) gives the eager result on
-    every replay, with eager calls on the same workspace in between."""
+    """A captured one-pass call replayed many times (the clearing fill is a
+    kernel node, replayed with it) gives the eager result on every replay,
+    with eager calls on the same workspace in between."""
     P = 1 << 20
     lw = torch.from_numpy(workloads.normal_logweights(P, 1.0, 16)).cuda()
     x = torch.from_numpy(workloads.state_rows_normal(P, 4, 1)).cuda()
