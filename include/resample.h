@@ -17,7 +17,8 @@
  *    before the kernels finish.
  *  - P = 0 is an empty resampling: RS_OK, nothing is launched or touched.
  *  - Argument errors are returned synchronously, before any launch:
- *      RS_EINVAL     null pointer, P < 0, P > 2^31 - 1, D < 1, overlapping
+ *      RS_EINVAL     null pointer, P < 0, P > 2^31 - 1, D < 1, P * D above
+ *                    2^40 state values (entry points that take rows), overlapping
  *                    input and output buffers, unknown resampler kind, a
  *                    workspace not 256-byte aligned (hipMalloc's blocks are);
  *      RS_EWORKSPACE workspace smaller than rs_workspace_bytes();

@@ -48,6 +48,10 @@ namespace {
 
 constexpr int64_t kMaxP = 2147483647;  // ancestors are int32
 
+// P rows of D binary32 values are at most 2^40 values (4 TiB), so byte
+// counts and element indices never overflow; callers have checked P >= 1.
+bool state_too_big(int64_t P, int32_t D) { return (size_t)D > ((size_t)1 << 40) / (size_t)P; }
+
 std::mutex g_tune_mutex;
 bool g_tune_init = false;
 rs::MetropolisTuning g_tune{256, 8, 16384, 0};
@@ -222,8 +226,8 @@ int resample_and_copy(int kind, const float *lw, int32_t *anc, int32_t *off, int
     if (P == 0) return RS_OK;
     if (!lw || !anc || !x_in || !x_out || D < 1 || P < 0 || P > kMaxP) return RS_EINVAL;
     if (off && kind != RS_STRATIFIED && kind != RS_SYSTEMATIC) return RS_EINVAL;
+    if (state_too_big(P, D)) return RS_EINVAL;
     const size_t p = (size_t)P, rows = p * (size_t)D * sizeof(float);
-    if ((size_t)D > ((size_t)1 << 40) / p) return RS_EINVAL;
     // written: anc, off, x_out; read: lw, x_in
     const void *outs[3] = {anc, off, x_out};
     const size_t out_bytes[3] = {4 * p, 4 * p, rows};
@@ -291,7 +295,8 @@ int permute_copy(const int32_t *anc, const float *x_in, float *x_out, int64_t P,
                  int32_t *status, hipStream_t stream)
 {
     if (P == 0) return RS_OK;
-    if (!anc || !x_in || !x_out || P < 0 || P > kMaxP || D < 1) return RS_EINVAL;
+    if (!anc || !x_in || !x_out || P < 0 || P > kMaxP || D < 1 || state_too_big(P, D))
+        return RS_EINVAL;
     const size_t rows = (size_t)P * (size_t)D * sizeof(float);
     if (overlaps(x_in, rows, x_out, rows) || overlaps(anc, 4 * (size_t)P, x_out, rows))
         return RS_EINVAL;
@@ -307,7 +312,9 @@ int offspring_update_inplace(const int32_t *off, float *x, int64_t P, int32_t D,
                              void *ws, size_t ws_bytes, int32_t *status, hipStream_t stream)
 {
     if (P == 0) return RS_OK;
-    if (!off || !x || !ws || misaligned(ws) || P < 0 || P > kMaxP || D < 1) return RS_EINVAL;
+    if (!off || !x || !ws || misaligned(ws) || P < 0 || P > kMaxP || D < 1 ||
+        state_too_big(P, D))
+        return RS_EINVAL;
     const size_t rows = (size_t)P * (size_t)D * sizeof(float), p4 = 4 * (size_t)P;
     if (overlaps(off, p4, x, rows)) return RS_EINVAL;
     if (anc && (overlaps(anc, p4, off, p4) || overlaps(anc, p4, x, rows))) return RS_EINVAL;

@@ -326,3 +326,49 @@ def test_static_entry_arguments_and_limit(L):
                                       None, None) == L.RS_EWORKSPACE
     assert lib.resample_prefix_static(0, None, f(0x90000), None, 0, 1, 0, None, None,
                                       None) == L.RS_OK  # empty: nothing to do
+
+
+def test_inplace_update_arguments(L):
+    # the minimal-copy update: its workspace size, and every argument error
+    # returned before a launch (the pointers are never dereferenced)
+    lib = L.lib
+    f = ctypes.c_void_p
+    assert lib.rs_inplace_workspace_bytes(0) == 0
+    sizes = [lib.rs_inplace_workspace_bytes(P) for P in (1, 1024, 1025, 1 << 20, 2**31 - 1)]
+    assert all(a <= b for a, b in zip(sizes, sizes[1:])) and sizes[0] > 0
+    P, D = 1000, 4
+    off, x, anc = f(0x100000), f(0x200000), f(0x300000)
+    ws, wsb = f(0x400000), lib.rs_inplace_workspace_bytes(P)
+    call = lib.offspring_update_inplace
+    assert call(None, None, 0, 0, None, None, 0, None, None) == L.RS_OK    # empty
+    assert call(None, x, P, D, anc, ws, wsb, None, None) == L.RS_EINVAL    # no counts
+    assert call(off, None, P, D, anc, ws, wsb, None, None) == L.RS_EINVAL  # no rows
+    assert call(off, x, P, D, anc, None, wsb, None, None) == L.RS_EINVAL   # no workspace
+    assert call(off, x, P, D, anc, f(0x400010), wsb, None, None) == L.RS_EINVAL  # misaligned
+    assert call(off, x, P, 0, anc, ws, wsb, None, None) == L.RS_EINVAL     # D < 1
+    assert call(off, x, -1, D, anc, ws, wsb, None, None) == L.RS_EINVAL
+    assert call(off, x, 2**31, D, anc, ws, wsb, None, None) == L.RS_EINVAL
+    assert call(off, f(0x100000 + 4 * P - 4), P, D, anc, ws, wsb, None, None) == L.RS_EINVAL
+    assert call(off, x, P, D, f(0x200000 + 16), ws, wsb, None, None) == L.RS_EINVAL  # anc in x
+    assert call(off, x, P, D, anc, ws, wsb - 1, None, None) == L.RS_EWORKSPACE
+    assert call(off, x, P, D, anc, f(0x300000), wsb, None, None) == L.RS_EINVAL  # ws over anc
+    # P * D beyond 2^40 state values is refused (no byte count overflows)
+    assert call(off, x, 2**31 - 1, 2**30, None, ws, 1 << 62, None, None) == L.RS_EINVAL
+    assert lib.permute_copy(off, x, f(0x900000000), 2**31 - 1, 2**30, None, None) == L.RS_EINVAL
+
+
+def test_prefix_path_selection(L):
+    # process-wide form of the stratified/systematic calls: unknown values are
+    # refused and leave the setting unchanged
+    lib = L.lib
+    saved = lib.rs_prefix_get_path()
+    try:
+        for path in (L.PATH_LAUNCHES, L.PATH_ONEPASS, L.PATH_AUTO):
+            assert lib.rs_prefix_set_path(path, -1) == L.RS_OK
+            assert lib.rs_prefix_get_path() == path
+        assert lib.rs_prefix_set_path(L.PATH_ONEPASS, 0) == L.RS_OK
+        for bad in (-1, 3, 99):
+            assert lib.rs_prefix_set_path(bad, -1) == L.RS_EINVAL
+            assert lib.rs_prefix_get_path() == L.PATH_ONEPASS
+    finally:
+        lib.rs_prefix_set_path(saved, -1)
