@@ -77,6 +77,7 @@ EPS = 0.01        # eq. (5) tolerance of the adaptive Metropolis leg
 B_MAX = 4096      # cap of the adaptive iteration count
 COLD_BYTES = 512 << 20  # every cold timing graph touches at least this much
 MALL_BYTES = 256 << 20
+L1_BYTES = 32 << 10  # a CU's vector L1
 
 
 def parse():
@@ -349,6 +350,12 @@ def profile_only(torch, rs, args, sets, families, step):
     only["gather_probe"] = lambda bs, k: rs.rs_probe_gather(sets[0]["lw"], 1 << 20, 8, k + 1,
                                                            out=probe_out)
     only["permute_copy_metropolis"] = only["permute_copy_random"]
+    if args.only == "batched_metropolis":  # the batched configuration's Metropolis half
+        from paper_1202_6163_amd import workloads
+        from paper_1202_6163_amd.batch import Batch
+        _, insts = batch_workload(torch, workloads, sets[0]["lw"].device)
+        half = Batch([d for d in insts if d["kind"] == "metropolis"])
+        only["batched_metropolis"] = lambda bs, k: half.run()
     fn = only[args.only]
     for k, bs in enumerate(sets):
         if args.only in ("inplace", "permute_copy_metropolis"):
@@ -890,13 +897,10 @@ def minimal_copy(torch, rs, workloads, P, B):
     return res
 
 
-def batched(torch, rs, workloads, args):
-    """1024 instances, P log-uniform in [2^8, 2^16], sigma in [0.25, 3],
-    Metropolis B = 64 and stratified alternating, D = 16: one batched graph
-    replay against the same work as per-instance calls (resample +
-    permute_copy) captured in one graph, and launched one by one."""
-    from paper_1202_6163_amd.batch import Batch
-    dev = torch.device("cuda", 0)
+def batch_workload(torch, workloads, dev):
+    """The batched configuration's 1024 instances (sizes, then the instance
+    dicts): P log-uniform in [2^8, 2^16], sigma in [0.25, 3], Metropolis B = 64
+    and stratified alternating, D = 16 rows."""
     P, sig = workloads.batch_instances(1024, seed=0)
     insts = []
     for k in range(len(P)):
@@ -907,6 +911,17 @@ def batched(torch, rs, workloads, args):
             kind="metropolis" if k % 2 else "stratified", B=64, seed=5, instance=k,
             x_in=torch.from_numpy(workloads.state_rows_normal(Pk, 16, k)).to(dev),
             x_out=torch.empty((Pk, 16), dtype=torch.float32, device=dev)))
+    return P, insts
+
+
+def batched(torch, rs, workloads, args):
+    """1024 instances, P log-uniform in [2^8, 2^16], sigma in [0.25, 3],
+    Metropolis B = 64 and stratified alternating, D = 16: one batched graph
+    replay against the same work as per-instance calls (resample +
+    permute_copy) captured in one graph, and launched one by one."""
+    from paper_1202_6163_amd.batch import Batch
+    dev = torch.device("cuda", 0)
+    P, insts = batch_workload(torch, workloads, dev)
     total = int(P.sum())
     G = Graphs(torch)
     b = Batch(insts)
@@ -929,9 +944,12 @@ def batched(torch, rs, workloads, args):
     torch.cuda.synchronize()
     eager_ms = (time.perf_counter() - t0) * 1e3
     tb, tp = pct(ms_b, 50), pct(ms_p, 50)
-    # the two halves on their own: the Metropolis instances against the L2
-    # request rate (one proposal gather per iteration), the stratified ones
-    # against HBM (lw twice, ancestors, the D = 16 copy: 12 + 4 + 128 B)
+    # the two halves on their own: the Metropolis instances' iterations per
+    # second set beside the L2 request peak (an instance whose weights fit a
+    # CU's 32 KB L1 is served partly there, so the ratio is not a roofline
+    # fraction and may exceed 1; the counters of the profiling family
+    # batched_metropolis give the L2 requests), the stratified ones against
+    # HBM (lw twice, ancestors, the D = 16 copy: 12 + 4 + 128 B)
     halves = {}
     for kind in ("metropolis", "stratified"):
         sub = [d for d in insts if d["kind"] == kind]
@@ -942,8 +960,10 @@ def batched(torch, rs, workloads, args):
         h = {"instances": len(sub), "particles": n_k, "ms_p50": msk}
         if kind == "metropolis":
             it = n_k * 64
+            l1_sized = sum(int(d["lw"].numel()) for d in sub if 4 * d["lw"].numel() <= L1_BYTES)
             h.update(iterations=it, iterations_per_s=it / (msk * 1e-3),
-                     frac_of_l2_request_peak=it / (msk * 1e-3) / (L2_PEAK_GREQ_S * 1e9))
+                     iterations_over_l2_request_peak=it / (msk * 1e-3) / (L2_PEAK_GREQ_S * 1e9),
+                     iteration_share_in_l1_sized_instances=l1_sized / n_k)
         else:
             by = n_k * (12 + 4 + 8 * 16)
             h.update(bytes=by, GB_per_s=by / (msk * 1e-3) / 1e9,
