@@ -167,6 +167,25 @@ def test_onepass_sizes_change_on_one_workspace(rs, path):
         same(ref, got, f"call {k}: {kind} P={P}")
 
 
+def test_onepass_after_other_kinds_on_one_workspace(rs, path):
+    """One buffer serves a multinomial call at 2^20 and one-pass stratified
+    calls at small P in turn. The multinomial's tile sections cover the small
+    layout's published words with its own values; the one-pass calls never
+    wait (wait bound 0: every block takes whatever valid-looking words it
+    finds on its first read) and must still equal the launches."""
+    big = 1 << 20
+    ws = torch.empty(rs.workspace_bytes(big, rs.MULTINOMIAL), dtype=torch.uint8, device="cuda")
+    lw_big = torch.from_numpy(workloads.normal_logweights(big, 1.0, 40)).cuda()
+    for k, P in enumerate([3000, 70001, 3000, 1025, 1 << 20]):
+        say(f"onepass after multinomial: call {k} P={P}")
+        rs.resample_multinomial(lw_big, k, 0, ws=ws)
+        lw = torch.from_numpy(workloads.normal_logweights(P, 2.0, 41 + k)).cuda()
+        ref = run(rs, "launches", "stratified", lw, k, 0)
+        got = run(rs, "onepass", "stratified", lw, k, 0,
+                  ws=ws[:rs.workspace_bytes(P, rs.STRATIFIED)], wait_ns=0)
+        same(ref, got, f"after multinomial, call {k}: P={P}")
+
+
 def test_onepass_graph_replays(rs, path):
     """A captured one-pass call replayed many times (the clearing fill is a
     kernel node, replayed with it) gives the eager result on every replay,
