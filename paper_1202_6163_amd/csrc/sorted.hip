@@ -23,8 +23,6 @@
 // Equal keys therefore keep their order in every pass, and the sort is
 // stable. The first pass reads the log-weights themselves and numbers the
 // particles.
-constexpr int kPasses = 4;
-constexpr int64_t kOwnScanBlocks = 64;  // up to this many blocks, no scan launch
 #include <hip/hip_runtime.h>
 
 #include "common.h"
@@ -39,6 +37,8 @@ constexpr int kSortThreads = 1024;                      // the sort kernels
 constexpr int kSortItems = 4;                           // elements per thread and block
 constexpr int kSortBlock = kSortThreads * kSortItems;   // 4096 elements per block
 constexpr int kRadix = 256;                             // eight bits per pass
+constexpr int kPasses = 4;                              // 32-bit keys
+constexpr int64_t kOwnScanBlocks = 64;                  // up to this many blocks, no scan launch
 constexpr int kSortWaves = kSortThreads / kWave;
 constexpr int kDigitWaves = kRadix / kWave;             // the waves that own a digit each lane
 static_assert(kRadix <= kSortThreads && kRadix % kWave == 0, "threads 0..255 own the digits");
