@@ -350,6 +350,11 @@ def profile_only(torch, rs, args, sets, families, step):
     only["gather_probe"] = lambda bs, k: rs.rs_probe_gather(sets[0]["lw"], 1 << 20, 8, k + 1,
                                                            out=probe_out)
     only["permute_copy_metropolis"] = only["permute_copy_random"]
+    off_ws = torch.empty(int(rs.lib.rs_offspring_workspace_bytes(sets[0]["lw"].numel())),
+                         dtype=torch.uint8, device=sets[0]["lw"].device)
+    only["offspring"] = lambda bs, k: rs.ancestors_to_offspring(bs["anc"], off=bs["off"])
+    only["offspring_ws"] = lambda bs, k: rs.ancestors_to_offspring_ws(bs["anc"], off=bs["off"],
+                                                                      ws=off_ws)
     if args.only == "batched_metropolis":  # the batched configuration's Metropolis half
         from paper_1202_6163_amd import workloads
         from paper_1202_6163_amd.batch import Batch
@@ -358,7 +363,7 @@ def profile_only(torch, rs, args, sets, families, step):
         only["batched_metropolis"] = lambda bs, k: half.run()
     fn = only[args.only]
     for k, bs in enumerate(sets):
-        if args.only in ("inplace", "permute_copy_metropolis"):
+        if args.only in ("inplace", "permute_copy_metropolis", "offspring", "offspring_ws"):
             # Metropolis ancestors (eq. (5)'s B) and their offspring
             families["metropolis"][0](bs, 900 + k)
             rs.ancestors_to_offspring(bs["anc"], off=bs["off"])
@@ -457,6 +462,7 @@ def headline(full, out_path):
     if "minimal_copy" in full:
         h["minimal_copy"] = {k: {m: v[m] for m in ("permute_copy_us", "inplace_us",
                                                      "anc_to_off_plus_inplace_us",
+                                                     "anc_to_off_ws_plus_inplace_us",
                                                      "bytes_ratio_vs_permute_copy")}
                              for k, v in full["minimal_copy"].items() if k.startswith("D")}
     if "serving" in full:
@@ -847,7 +853,8 @@ def minimal_copy(torch, rs, workloads, P, B):
     """The state update after Metropolis (random ancestors, eq. (5)'s B) at P,
     D = 4 and 16, cold: the ancestor-indexed copy into a second buffer
     against the in-place minimal-copy update (offspring form), with and
-    without the ancestors-to-offspring conversion. Algorithmic HBM bytes per
+    without the ancestors-to-offspring conversion (atomic form, and the
+    workspace form with one reused workspace). Algorithmic HBM bytes per
     particle: copy 4 + 8D; in place 8D per hole + 8 (the counts read twice)
     + 4 (a source tile's counts), the conversion 12 (ancestors read, counts
     cleared and counted)."""
@@ -869,11 +876,19 @@ def minimal_copy(torch, rs, workloads, P, B):
                                            dtype=torch.uint8, device=dev)})
             del lw
         holes = float(np.mean([(bs["off"] == 0).float().mean().item() for bs in sets]))
+        off_ws = torch.empty(int(rs.lib.rs_offspring_workspace_bytes(P)), dtype=torch.uint8,
+                             device=dev)
         forms = {
             "permute_copy_us": lambda bs: rs.permute_copy(bs["anc"], bs["x"], x_out=bs["xo"]),
             "inplace_us": lambda bs: rs.offspring_update_inplace(bs["off"], bs["x"], ws=bs["ws"]),
+            "anc_to_off_us": lambda bs: rs.ancestors_to_offspring(bs["anc"], off=bs["off2"]),
+            "anc_to_off_ws_us": lambda bs: rs.ancestors_to_offspring_ws(bs["anc"], off=bs["off2"],
+                                                                        ws=off_ws),
             "anc_to_off_plus_inplace_us": lambda bs: (
                 rs.ancestors_to_offspring(bs["anc"], off=bs["off2"]),
+                rs.offspring_update_inplace(bs["off2"], bs["x"], ws=bs["ws"])),
+            "anc_to_off_ws_plus_inplace_us": lambda bs: (
+                rs.ancestors_to_offspring_ws(bs["anc"], off=bs["off2"], ws=off_ws),
                 rs.offspring_update_inplace(bs["off2"], bs["x"], ws=bs["ws"])),
         }
         out = {"holes_fraction": holes, "buffer_sets": n_sets}
@@ -891,8 +906,9 @@ def minimal_copy(torch, rs, workloads, P, B):
         res[f"D{D}"] = out
         log(f"minimal_copy D={D}: holes {holes:.3f}; copy {out['permute_copy_us']:.1f} us, "
             f"in place {out['inplace_us']:.1f} us, with conversion "
-            f"{out['anc_to_off_plus_inplace_us']:.1f} us")
-        del sets
+            f"{out['anc_to_off_plus_inplace_us']:.1f} us (workspace form "
+            f"{out['anc_to_off_ws_plus_inplace_us']:.1f} us)")
+        del sets, off_ws
         torch.cuda.empty_cache()
     return res
 

@@ -235,6 +235,21 @@ int ancestors_to_offspring(const int32_t *anc, int32_t *off, int64_t P, int32_t 
                            hipStream_t stream);
 
 /*
+ * The same offspring counts (bit for bit, flags included) through a
+ * workspace: the ancestors are grouped by buckets of particles, then each
+ * bucket's counts are formed on chip and written whole, so random ancestors
+ * cost no device-scope atomics and off needs no clearing. Four launches;
+ * graph-capturable. Beyond P = 2^24, rs_offspring_workspace_bytes is 0 and the
+ * call runs as ancestors_to_offspring (ws may then be NULL).
+ *   ws     [device] workspace of ws_bytes >= rs_offspring_workspace_bytes(P),
+ *          256-byte aligned; must not overlap anc or off
+ * Errors: RS_EINVAL, RS_EWORKSPACE, RS_EHIP.
+ */
+size_t rs_offspring_workspace_bytes(int64_t P);
+int ancestors_to_offspring_ws(const int32_t *anc, int32_t *off, int64_t P, void *ws,
+                              size_t ws_bytes, int32_t *status, hipStream_t stream);
+
+/*
  * Ancestor-indexed copy of particle state: x_out[i, :] = x_in[a_i, :], bit for
  * bit, rows of D binary32 values, row-major. x_in and x_out must not overlap.
  * Rows whose ancestor lies outside [0, P) are zero-filled and flagged

@@ -83,6 +83,8 @@ def _load():
         "resample_prefix_static": (ctypes.c_int, [ctypes.c_int, vp, vp, vp, i64, u64, u32, vp,
                                                   i32p, vp]),
         "ancestors_to_offspring": (ctypes.c_int, [vp, vp, i64, i32p, vp]),
+        "rs_offspring_workspace_bytes": (sz, [i64]),
+        "ancestors_to_offspring_ws": (ctypes.c_int, [vp, vp, i64, vp, sz, i32p, vp]),
         "resample_and_copy": (ctypes.c_int, [ctypes.c_int, vp, vp, vp, i64, u32, u64, u32, vp, vp,
                                              ctypes.c_int32, vp, sz, i32p, vp]),
         "rs_sorted_workspace_bytes": (sz, [i64, ctypes.c_int]),

@@ -58,10 +58,14 @@ def workspace(P, kind, device=None, stream=None):
     The library leaves a workspace reusable after every call, so one buffer
     serves all calls ordered on the same stream.
     """
+    return _pooled(workspace_bytes(P, kind), device, stream)
+
+
+def _pooled(need, device=None, stream=None):
+    """The (device, stream) pool's buffer, grown to at least `need` bytes."""
     device = torch.device(device) if device is not None else torch.device(
         "cuda", torch.cuda.current_device())
     s = stream if stream is not None else torch.cuda.current_stream(device)
-    need = workspace_bytes(P, kind)
     key = (device.index, s.cuda_stream)
     buf = _workspaces.get(key)
     if buf is None or buf.numel() < need:
@@ -223,6 +227,24 @@ def ancestors_to_offspring(anc, off=None, status=None, stream=None):
     _need(off, torch.int32, "off", P)
     check(lib.ancestors_to_offspring(_ptr(anc), _ptr(off), P, _status_ptr(status),
                                      _stream_handle(stream)), "ancestors_to_offspring")
+    return off
+
+
+def ancestors_to_offspring_ws(anc, off=None, ws=None, status=None, stream=None):
+    """Offspring counts through a workspace (no device-scope atomics); ws
+    defaults to the (device, stream) pool's buffer."""
+    _need(anc, torch.int32, "anc")
+    P = anc.numel()
+    off = torch.empty(P, dtype=torch.int32, device=anc.device) if off is None else off
+    _need(off, torch.int32, "off", P)
+    need = int(lib.rs_offspring_workspace_bytes(P))
+    if ws is None and need > 0:
+        ws = _pooled(need, anc.device, stream)
+    if ws is not None:
+        _need(ws, torch.uint8, "ws")
+    check(lib.ancestors_to_offspring_ws(_ptr(anc), _ptr(off), P, _ptr(ws),
+                                        0 if ws is None else ws.numel(), _status_ptr(status),
+                                        _stream_handle(stream)), "ancestors_to_offspring_ws")
     return off
 
 

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libresample.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 SOURCES = ["capi.cpp", "batch_plan.cpp", "prefix.hip", "metropolis.hip", "misc.hip", "filter.hip",
-           "batch.hip", "probe.hip", "sorted.hip", "inplace.hip"]
+           "batch.hip", "probe.hip", "sorted.hip", "inplace.hip", "offspring.hip"]
 
 ARCH = "gfx950"
 FLAGS = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",

@@ -291,6 +291,23 @@ int ancestors_to_offspring(const int32_t *anc, int32_t *off, int64_t P, int32_t 
     return map_rc(rs::launch_offspring(anc, off, P, status, stream));
 }
 
+size_t rs_offspring_workspace_bytes(int64_t P) { return rs::offspring_workspace_bytes(P); }
+
+int ancestors_to_offspring_ws(const int32_t *anc, int32_t *off, int64_t P, void *ws,
+                              size_t ws_bytes, int32_t *status, hipStream_t stream)
+{
+    if (P == 0) return RS_OK;
+    if (!anc || !off || P < 0 || P > kMaxP) return RS_EINVAL;
+    const size_t p4 = 4 * (size_t)P, need = rs_offspring_workspace_bytes(P);
+    if (overlaps(anc, p4, off, p4)) return RS_EINVAL;
+    if (need > 0) {
+        if (!ws || misaligned(ws)) return RS_EINVAL;
+        if (ws_bytes < need) return RS_EWORKSPACE;
+        if (overlaps(ws, ws_bytes, anc, p4) || overlaps(ws, ws_bytes, off, p4)) return RS_EINVAL;
+    }
+    return map_rc(rs::launch_offspring_ws(anc, off, P, ws, status, stream));
+}
+
 int permute_copy(const int32_t *anc, const float *x_in, float *x_out, int64_t P, int32_t D,
                  int32_t *status, hipStream_t stream)
 {

@@ -92,6 +92,13 @@ const uint32_t *adaptive_B_slot(const void *ws);
 int launch_offspring(const int32_t *anc, int32_t *off, int64_t P, int32_t *status,
                      hipStream_t stream);
 
+// The same counts through a workspace without device-scope atomics
+// (offspring.hip): its bytes (0 beyond 2^24 particles, where the launcher
+// takes launch_offspring) and the four launches.
+size_t offspring_workspace_bytes(int64_t P);
+int launch_offspring_ws(const int32_t *anc, int32_t *off, int64_t P, void *ws, int32_t *status,
+                        hipStream_t stream);
+
 int launch_permute_copy(const int32_t *anc, const float *x_in, float *x_out, int64_t P, int32_t D,
                         int32_t *status, hipStream_t stream);
 

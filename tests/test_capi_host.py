@@ -372,3 +372,28 @@ def test_prefix_path_selection(L):
             assert lib.rs_prefix_get_path() == L.PATH_ONEPASS
     finally:
         lib.rs_prefix_set_path(saved, -1)
+
+
+def test_offspring_ws_arguments(L):
+    # the workspace form of ancestors_to_offspring: its size (0 beyond 2^24,
+    # where it runs as the plain conversion) and argument errors before any launch
+    lib = L.lib
+    f = ctypes.c_void_p
+    assert lib.rs_offspring_workspace_bytes(0) == 0
+    assert lib.rs_offspring_workspace_bytes(1) > 0
+    assert lib.rs_offspring_workspace_bytes(1 << 24) >= 4 << 24
+    assert lib.rs_offspring_workspace_bytes((1 << 24) + 1) == 0
+    P = 5000
+    need = lib.rs_offspring_workspace_bytes(P)
+    anc, off, ws = f(0x100000), f(0x200000), f(0x300000)
+    call = lib.ancestors_to_offspring_ws
+    assert call(None, None, 0, None, 0, None, None) == L.RS_OK           # empty
+    assert call(None, off, P, ws, need, None, None) == L.RS_EINVAL
+    assert call(anc, None, P, ws, need, None, None) == L.RS_EINVAL
+    assert call(anc, off, -1, ws, need, None, None) == L.RS_EINVAL
+    assert call(anc, off, 2**31, ws, need, None, None) == L.RS_EINVAL
+    assert call(anc, f(0x100000 + 4 * P - 4), P, ws, need, None, None) == L.RS_EINVAL
+    assert call(anc, off, P, None, need, None, None) == L.RS_EINVAL        # no workspace
+    assert call(anc, off, P, f(0x300010), need, None, None) == L.RS_EINVAL  # misaligned
+    assert call(anc, off, P, ws, need - 1, None, None) == L.RS_EWORKSPACE
+    assert call(anc, off, P, f(0x200000), need, None, None) == L.RS_EINVAL  # ws over off

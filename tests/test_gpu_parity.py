@@ -445,6 +445,61 @@ def test_offspring_bad_ancestor(rs):
     assert np.array_equal(off, [1, 1, 2, 0, 0, 1])  # -1 skipped, 5 counted
 
 
+# the workspace form: bucket widths 2^12 .. 2^15, one and many buckets and
+# blocks, ragged last bucket, and past 2^24 the plain conversion
+@pytest.mark.parametrize("P", [1, 63, 4095, 4096, 4097, 100003, 1 << 20, (1 << 20) + 3,
+                               3000001, 1 << 24, (1 << 24) + 1])
+def test_offspring_ws_bit_exact(rs, P):
+    rng = np.random.default_rng(P + 7)
+    heavy = rng.integers(0, P, P)
+    heavy[rng.random(P) < 0.6] = P // 7  # one particle takes most of the draws
+    pats = {"random": rng.integers(0, P, P), "sorted": np.sort(rng.integers(0, P, P)),
+            "one": np.full(P, P // 2), "last": np.full(P, P - 1),
+            "few": rng.choice(np.array([0, P // 3, P - 1]), size=P), "heavy": heavy}
+    for name, anc in pats.items():
+        anc = anc.astype(np.int32)
+        ref, _ = oracle.ancestors_to_offspring(anc)
+        got = host(rs.ancestors_to_offspring_ws(dev(anc)))
+        assert np.array_equal(got, ref), f"{name} P={P}: differs at {np.flatnonzero(got != ref)[:5]}"
+
+
+def test_offspring_ws_bad_ancestors_and_graph_replays(rs):
+    anc = np.array([0, 1, 5, -1, 2, 2], dtype=np.int32)
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    off = host(rs.ancestors_to_offspring_ws(dev(anc), status=st))
+    assert int(host(st)[0]) == rs.FLAG_BAD_ANCESTOR
+    assert np.array_equal(off, [1, 1, 2, 0, 0, 1])  # -1 skipped, 5 counted
+    P = 100003
+    rng = np.random.default_rng(5)
+    anc = rng.integers(0, P, P).astype(np.int32)
+    anc[[7, 500, 99999]] = [-5, P, P + 10]
+    st.zero_()
+    got = host(rs.ancestors_to_offspring_ws(dev(anc), status=st))
+    assert int(host(st)[0]) == rs.FLAG_BAD_ANCESTOR
+    st2 = torch.zeros(1, dtype=torch.int32, device="cuda")
+    assert np.array_equal(got, host(rs.ancestors_to_offspring(dev(anc), status=st2)))
+    assert int(host(st2)[0]) == rs.FLAG_BAD_ANCESTOR
+    # captured once, replayed on new ancestors written in place between replays
+    P = (1 << 20) + 3
+    a = torch.zeros(P, dtype=torch.int32, device="cuda")
+    off = torch.full((P,), -1, dtype=torch.int32, device="cuda")
+    ws = torch.empty(int(rs.lib.rs_offspring_workspace_bytes(P)), dtype=torch.uint8, device="cuda")
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        rs.ancestors_to_offspring_ws(a, off=off, ws=ws)
+    for k in range(4):
+        anc = np.random.default_rng(40 + k).integers(0, P >> k, P).astype(np.int32)
+        a.copy_(dev(anc))
+        off.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        ref, _ = oracle.ancestors_to_offspring(anc)
+        assert np.array_equal(host(off), ref), f"replay {k}"
+
+
 # every D up to 100003 particles; at the full size the D of the sweep (4) and D = 1
 COPY_CASES = [(P, D) for P in (1, 5, 1023, 4096, 100003) for D in (1, 3, 4, 8, 12, 16, 32)]
 COPY_CASES += [(1 << 20, 1), (1 << 20, 4), (1 << 20, 16)]
