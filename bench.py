@@ -1166,7 +1166,8 @@ def cpu_baseline(torch, rs, args, workloads):
             oracle.permute_copy(gpu["metropolis"], x)
             t_met.append(t1 - t0)
             t_rest.append(time.perf_counter() - t1)
-            if time.perf_counter() - t_start > args.cpu_seconds or len(t_met) >= 10:
+            # a bounded sample: passes until the time budget (default 15 s) is spent
+            if time.perf_counter() - t_start > args.cpu_seconds or len(t_met) >= 100:
                 break
     finally:
         if allowed:
