@@ -18,7 +18,7 @@ The LAST line on stdout is a compact JSON headline (a few KB): value,
 per-step times, the dominant kernel's roofline, the scan + copy path against
 HBM, the CPU baseline with its parity check, and short summaries of the
 other sections. The full results go to --out (default
-gpurun_out/bench_full.json):
+results/bench_full.json):
   per_call      cold per-call times of every call family, with the bytes
                 each timing graph touches (all above the Infinity Cache);
   step_fixed_B  the same step with Metropolis at a fixed B (flagged when B
@@ -103,7 +103,7 @@ def parse():
                     help="seconds of Poisson arrivals at 2000 req/s (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--only", type=str, default="", help="time one kernel (for profiling)")
-    ap.add_argument("--out", type=str, default=os.path.join("gpurun_out", "bench_full.json"))
+    ap.add_argument("--out", type=str, default=os.path.join("results", "bench_full.json"))
     ap.add_argument("--record-traffic", type=str, default="",
                     help="write profiles/traffic.json from the rocprofv3 counter runs under "
                          "this directory (subdirectories <family>_<COUNTER>) and exit")

@@ -16,7 +16,7 @@ def pytest_sessionfinish(session, exitstatus):
         return
     import json
     path = os.environ.get("RS_PARITY_REPORT",
-                          os.path.join(ROOT, "gpurun_out", "parity_report.json"))
+                          os.path.join(ROOT, "results", "parity_report.json"))
     os.makedirs(os.path.dirname(path), exist_ok=True)
     with open(path, "w") as f:
         json.dump({"summary": parity.summary(), "exitstatus": int(exitstatus),
