@@ -78,7 +78,8 @@ def same(a, b, what):
             assert u == v, f"{what}: output {k}: {u} vs {v}"
 
 
-SIZES = [1, 3, 1000, 1024, 1025, 2048, 4099, 65536 + 7, (1 << 18) - 1, 1 << 20]
+SIZES = [1, 3, 1000, 1024, 1025, 2048, 4099, 65536 + 7, (1 << 18) - 1, 1 << 20,
+         (1 << 20) + 1]  # past 1024 tiles the one-pass path falls back to the launches
 
 
 @pytest.mark.parametrize("kind", KINDS)
