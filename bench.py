@@ -479,7 +479,7 @@ def headline(full, out_path):
     h["full_results"] = out_path
     h = _round_floats(h)
     line = json.dumps(h)
-    for drop in ("serving", "per_call_us", "crossover_sigma_by_P", "batched"):
+    for drop in ("per_call_us", "crossover_sigma_by_P", "serving", "batched"):
         if len(line) <= 4000:
             break
         h.pop(drop, None)
