@@ -162,3 +162,26 @@ def test_without_slots_and_graph_replays(rs):
         g.replay()
         torch.cuda.synchronize()
         assert np.array_equal(x.cpu().numpy(), xo), f"replay {k}"
+
+
+@pytest.mark.parametrize("D", [4, 8, 32])
+def test_unaligned_rows_and_wide_rows(rs, D):
+    """Rows one float past a 16-byte boundary take the scalar path; D = 8 and
+    32 the vector path with more vectors per row. Same bits either way."""
+    P = 70001
+    lw = workloads.normal_logweights(P, 2.0, 34)
+    anc, _ = oracle.stratified(lw, 3, 0)
+    off_h, _ = oracle.ancestors_to_offspring(anc)
+    x_h = workloads.state_rows_exact(P, D)
+    xo, ao, rc = oracle.offspring_update_inplace(off_h, x_h)
+    assert rc == 0
+    for aligned in (True, False):
+        buf = torch.zeros(P * D + 1, dtype=torch.float32, device="cuda")
+        x = (buf[:P * D] if aligned else buf[1:]).view(P, D)
+        x.copy_(torch.from_numpy(x_h).cuda())
+        a = torch.full((P,), -5, dtype=torch.int32, device="cuda")
+        rs.offspring_update_inplace(torch.from_numpy(off_h).cuda(), x, anc=a)
+        torch.cuda.synchronize()
+        assert np.array_equal(x.cpu().numpy().view(np.uint32), xo.view(np.uint32)), \
+            f"D={D} aligned={aligned}: rows differ"
+        assert np.array_equal(a.cpu().numpy(), ao), f"D={D} aligned={aligned}: slots differ"

@@ -653,6 +653,36 @@ def test_resample_and_copy_equals_separate_calls(rs, kind, P, D):
 
 
 @pytest.mark.parametrize("kind", ["metropolis"] + PREFIX)
+@pytest.mark.parametrize("D", [1, 2, 5, 32])
+@pytest.mark.parametrize("P", [1025, 70001])
+@pytest.mark.parametrize("aligned", [True, False])
+def test_resample_and_copy_row_widths(rs, kind, D, P, aligned):
+    # more row widths, and state views that are not 16-byte aligned (the
+    # copy's scalar path): the rows equal the oracle's copy of the ancestors,
+    # which equal the plain call's
+    seed, inst = 13, 2
+    lw = dev(workloads.normal_logweights(P, 1.0, seed))
+    rows = workloads.state_rows_exact(P, D)
+    if aligned:
+        x = dev(rows)
+        xo = torch.full((P, D), -1.0, dtype=torch.float32, device="cuda")
+    else:  # one float past a 16-byte boundary, in and out
+        buf_in = torch.zeros(P * D + 1, dtype=torch.float32, device="cuda")
+        buf_in[1:].copy_(dev(rows).reshape(-1))
+        x = buf_in[1:].view(P, D)
+        xo = torch.full((P * D + 1,), -1.0, dtype=torch.float32, device="cuda")[1:].view(P, D)
+    anc, xo = rs.resample_and_copy(kind, lw, x, seed, inst, B=24, x_out=xo)
+    if kind == "metropolis":
+        ref = rs.resample_metropolis(lw, 24, seed, inst)
+    else:
+        ref = getattr(rs, f"resample_{kind}")(lw, seed, inst)
+    assert torch.equal(anc, ref)
+    want, rc = oracle.permute_copy(host(anc), rows)
+    assert rc == 0
+    assert np.array_equal(host(xo).view(np.int32), want.view(np.int32))
+
+
+@pytest.mark.parametrize("kind", ["metropolis"] + PREFIX)
 def test_resample_and_copy_full_size_against_oracle(rs, kind):
     # the benchmark step's form and size: P = 2^20, D = 4, one shared
     # multinomial-sized workspace, offspring for stratified/systematic
