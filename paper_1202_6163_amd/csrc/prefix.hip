@@ -80,8 +80,10 @@ __global__ __launch_bounds__(kTileThreads) void table_kernel(int64_t P, uint64_t
 }
 
 // Stratified/systematic tables with LDS boundaries split the counts over up
-// to kTableParts blocks; the rest run one block.
-constexpr int64_t kTableParts = 8;
+// to kTableParts blocks (one tile per thread up to 2^24 particles); the rest
+// run one block. The split changes no result: each block rebuilds the same
+// boundaries and the counts are exact.
+constexpr int64_t kTableParts = 64;
 
 template <int KIND>
 int launch_table(int64_t P, uint64_t seed, uint32_t instance, char *w, int32_t *status,
@@ -376,7 +378,7 @@ __global__ __launch_bounds__(kTileThreads) void onepass_kernel(
         m = fmaxf(m, mt[k]);
     }
     __syncthreads();  // sh_bound (part of the payload space) is written below
-    const TableSums sums = boundaries_tail(ws, n, t0, t1, true, fl, m, mt, S, sh_bound);
+    const TableSums sums = boundaries_tail<false>(ws, n, t0, t1, true, fl, m, mt, S, sh_bound);
     if (b == 0 && tid == 0) {
         WsHeader *h = ws.h;
         h->flags = sums.flags;
@@ -559,7 +561,7 @@ __global__ __launch_bounds__(kTileThreads) void cumulative_kernel(const float *_
     double W;
     const double *bound = ws.bound;
     if (FUSED) {
-        const TableSums sums = boundaries(ws, P, sh_bound);
+        const TableSums sums = boundaries<false>(ws, P, sh_bound);
         flags = sums.flags;
         m = sums.m;
         W = sums.W;
@@ -976,7 +978,7 @@ __global__ __launch_bounds__(kTileThreads) void multinomial_small_kernel(
     for (int64_t t = 0; t < n; ++t) tile_reduce_body(lw, P, t, ws_raw);
     __threadfence_block();
     __syncthreads();
-    const TableSums sums = boundaries(ws, P, sh_bound);
+    const TableSums sums = boundaries<false>(ws, P, sh_bound);
     if (threadIdx.x == 0) {
         WsHeader *h = ws.h;
         h->flags = sums.flags;

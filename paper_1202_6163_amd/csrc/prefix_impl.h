@@ -266,10 +266,19 @@ struct TableSums {
 constexpr int kRegTiles = 4;
 constexpr int kRunBatch = 8;  // a thread's run is read this many entries at a time
 
+// Tiles each thread loads per 16-byte vector group in the long-run passes,
+// and groups in flight at once.
+constexpr int kLoadGroups = 4;
+
 // The boundaries once each thread holds its run's tile values: in
 // registers (reg: mt, S for tiles t0 .. t1-1, at most kRegTiles) or, for
 // longer runs, the sums in bound[] and the maxima in ws.tile_max; fl and m
-// are the thread's OR of flags and max over its run.
+// are the thread's OR of flags and max over its run. LONG: callers that may
+// pass more than 1024 tiles (the table launches), where the element-wise
+// passes load 16-byte vectors, kLoadGroups groups at a time; the other
+// callers keep the compact strided loops (same operations on every value,
+// so the same bits, with fewer registers).
+template <bool LONG>
 __device__ __forceinline__ TableSums boundaries_tail(const WsView &ws, int64_t n, int64_t t0, int64_t t1,
                                             bool reg, int fl, float m, float mt[kRegTiles],
                                             double S[kRegTiles], double *bound);
@@ -288,6 +297,7 @@ __device__ __forceinline__ void tile_run(int64_t n, int64_t *t0, int64_t *t1, bo
     *t1 = min(n, *t0 + per);
 }
 
+template <bool LONG>
 __device__ inline TableSums boundaries(const WsView &ws, int64_t P, double *bound)
 {
     const int64_t n = num_tiles(P);
@@ -323,10 +333,45 @@ __device__ inline TableSums boundaries(const WsView &ws, int64_t P, double *boun
         }
 #pragma unroll
         for (int k = 0; k < kRegTiles; ++k) m = fmaxf(m, mt[k]);
+    } else if (LONG) {
+        // longer runs: the element-wise passes go block-wide (four
+        // consecutive tiles per thread and 16-byte vectors, kLoadGroups
+        // groups issued before the first is used; the sections are 256-byte
+        // aligned); only the sums below follow each thread's contiguous run.
+        // The maximum and the OR do not depend on the order they are taken in.
+        constexpr int64_t span = 4 * kTileThreads;
+        const int64_t n4 = n & ~(int64_t)3;
+        for (int64_t c = 4 * (int64_t)tid; c < n4; c += span * kLoadGroups) {
+            float4 mv[kLoadGroups];
+            int4 fv[kLoadGroups];
+            double2 sv[2 * kLoadGroups];
+#pragma unroll
+            for (int j = 0; j < kLoadGroups; ++j) {
+                const int64_t t = c + j * span, tc = t < n4 ? t : 0;  // reads stay in the arrays
+                mv[j] = *reinterpret_cast<const float4 *>(ws.tile_max + tc);
+                fv[j] = *reinterpret_cast<const int4 *>(ws.tile_flags + tc);
+                sv[2 * j] = *reinterpret_cast<const double2 *>(ws.tile_sum + tc);
+                sv[2 * j + 1] = *reinterpret_cast<const double2 *>(ws.tile_sum + tc + 2);
+            }
+#pragma unroll
+            for (int j = 0; j < kLoadGroups; ++j) {
+                const int64_t t = c + j * span;
+                if (t < n4) {
+                    fl |= fv[j].x | fv[j].y | fv[j].z | fv[j].w;
+                    m = fmaxf(m, fmaxf(fmaxf(mv[j].x, mv[j].y), fmaxf(mv[j].z, mv[j].w)));
+                    bound[t] = sv[2 * j].x;
+                    bound[t + 1] = sv[2 * j].y;
+                    bound[t + 2] = sv[2 * j + 1].x;
+                    bound[t + 3] = sv[2 * j + 1].y;
+                }
+            }
+        }
+        for (int64_t t = n4 + tid; t < n; t += kTileThreads) {
+            fl |= ws.tile_flags[t];
+            m = fmaxf(m, ws.tile_max[t]);
+            bound[t] = ws.tile_sum[t];
+        }
     } else {
-        // longer runs: the element-wise passes go block-strided (coalesced
-        // loads, many independent ones in flight); only the sums below follow
-        // each thread's contiguous run
 #pragma unroll 8
         for (int64_t t = tid; t < n; t += kTileThreads) {
             fl |= ws.tile_flags[t];
@@ -334,9 +379,10 @@ __device__ inline TableSums boundaries(const WsView &ws, int64_t P, double *boun
             bound[t] = ws.tile_sum[t];
         }
     }
-    return boundaries_tail(ws, n, t0, t1, reg, fl, m, mt, S, bound);
+    return boundaries_tail<LONG>(ws, n, t0, t1, reg, fl, m, mt, S, bound);
 }
 
+template <bool LONG>
 __device__ __forceinline__ TableSums boundaries_tail(const WsView &ws, int64_t n, int64_t t0, int64_t t1,
                                             bool reg, int fl, float m, float mt[kRegTiles],
                                             double S[kRegTiles], double *bound)
@@ -373,12 +419,38 @@ __device__ __forceinline__ TableSums boundaries_tail(const WsView &ws, int64_t n
             }
         }
     } else {
-#pragma unroll 8
-        for (int64_t t = tid; t < n; t += kTileThreads) {
-            const float mc = ws.tile_max[t];
+        const auto rescale = [&](int64_t t, float mc) {
             bound[t] = (mc > -INFINITY) ? bound[t] * exp((double)mc - (double)m) : 0.0;
+        };
+        if (LONG) {
+            // the tiles this thread loaded above, their maxima read again
+            // (now from L2) as 16-byte vectors, kLoadGroups groups at a time
+            constexpr int64_t span = 4 * kTileThreads;
+            const int64_t n4 = n & ~(int64_t)3;
+            for (int64_t c = 4 * (int64_t)tid; c < n4; c += span * kLoadGroups) {
+                float4 mv[kLoadGroups];
+#pragma unroll
+                for (int j = 0; j < kLoadGroups; ++j) {
+                    const int64_t t = c + j * span;
+                    mv[j] = *reinterpret_cast<const float4 *>(ws.tile_max + (t < n4 ? t : 0));
+                }
+#pragma unroll
+                for (int j = 0; j < kLoadGroups; ++j) {
+                    const int64_t t = c + j * span;
+                    if (t < n4) {
+                        rescale(t, mv[j].x);
+                        rescale(t + 1, mv[j].y);
+                        rescale(t + 2, mv[j].z);
+                        rescale(t + 3, mv[j].w);
+                    }
+                }
+            }
+            for (int64_t t = n4 + tid; t < n; t += kTileThreads) rescale(t, ws.tile_max[t]);
+        } else {
+#pragma unroll 8
+            for (int64_t t = tid; t < n; t += kTileThreads) rescale(t, ws.tile_max[t]);
         }
-        __syncthreads();  // the runs below cross the strided ownership (reg is uniform)
+        __syncthreads();  // the runs below cross the element-wise ownership (reg is uniform)
         for (int64_t c = t0; c < t1; c += kRunBatch) {
             double v[kRunBatch];
 #pragma unroll
@@ -470,7 +542,7 @@ __device__ void table_body(int64_t P, uint64_t seed, uint32_t instance, char *ws
     const int64_t n = num_tiles(P);
     const int tid = threadIdx.x;
     const bool staged = bound != ws.bound;
-    const TableSums sums = boundaries(ws, P, bound);
+    const TableSums sums = boundaries<true>(ws, P, bound);
     if (sums.flags) {
         if (tid == 0 && part == 0) {
             h->flags = sums.flags;
@@ -870,7 +942,7 @@ __device__ void fill_body(const float *__restrict__ lw, int32_t *__restrict__ an
     float m;
     double W;
     if (FUSED) {
-        const TableSums sums = boundaries(ws, P, sh_bound);
+        const TableSums sums = boundaries<false>(ws, P, sh_bound);
         flags = sums.flags;
         m = sums.m;
         W = sums.W;
