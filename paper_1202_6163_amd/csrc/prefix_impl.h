@@ -743,14 +743,17 @@ __device__ __forceinline__ int64_t first_bound_above(const double *bound, int64_
 // o_j is the width of j's run (0 without one); otherwise (a tile whose draws
 // spill into overflow windows) o_j = N(C'_j) - N(C'_{j-1}) with N the draw
 // count below a point, C'_{-1} = B_{t-1} and N(B_{t-1}) = lo. Both give the
-// exact counts of the ancestors the fill writes. Called by the whole block.
+// exact counts of the ancestors the fill writes. Called by the whole block,
+// after a barrier that follows the searches: the run marks of the first form
+// reuse the LDS of Cs, which that form no longer reads.
 template <int KIND>
 __device__ void tile_offspring(int32_t *off, int64_t P, int64_t t, int64_t lo, int64_t hi,
                                int64_t oe, int64_t a0, const int32_t a[8],
-                               const int32_t *sh_anc, const double *Cs, double W, double delta,
+                               const int32_t *sh_anc, double *Cs, double W, double delta,
                                uint64_t seed, uint32_t instance, double u_sys)
 {
-    __shared__ int16_t sh_start[kTile], sh_stop[kTile];
+    static_assert(2 * kTile * sizeof(int16_t) <= kTile * sizeof(double), "marks fit in Cs");
+    int16_t *const sh_start = reinterpret_cast<int16_t *>(Cs), *const sh_stop = sh_start + kTile;
     const int64_t base = t * kTile;
     const int64_t j0 = base + 4 * (int64_t)threadIdx.x;
     int32_t o[4];
