@@ -12,7 +12,7 @@
 // Design on MI355X.
 //  1. tile_reduce_kernel streams lw once: per 1024-weight tile the max, the
 //     sum of exp(lw - tile max) in binary64 and the data flags.
-//  2. table_kernel (up to 8 blocks): the tile sums rescaled to the global
+//  2. table_kernel (up to 64 blocks): the tile sums rescaled to the global
 //     max and scanned into the tile boundaries B_t, the number of draw points
 //     below each boundary (stratified/systematic draws are non-decreasing, so
 //     this is a short search near B / (W/P)) and the owners of the overflow
