@@ -63,20 +63,18 @@ __global__ __launch_bounds__(kTileThreads) void tile_reduce_kernel(const float *
     tile_reduce_body(lw, P, blockIdx.x, ws_raw);
 }
 
-template <int KIND, bool LDS>
-__global__ __launch_bounds__(kTileThreads) void table_kernel(int64_t P, uint64_t seed,
-                                                             uint32_t instance, char *ws_raw,
-                                                             int32_t *status, double *lse_out,
-                                                             double eps, uint32_t B_max,
-                                                             uint32_t *B_used)
+template <int KIND, bool LDS, int NT>
+__global__ __launch_bounds__(NT) void table_kernel(int64_t P, uint64_t seed, uint32_t instance,
+                                                   char *ws_raw, int32_t *status, double *lse_out,
+                                                   double eps, uint32_t B_max, uint32_t *B_used)
 {
     extern __shared__ double sh_tab[];  // [n] boundaries, then the block's counts
     const WsView ws = ws_view(ws_raw, P);
     const int64_t n = num_tiles(P);
     double *bound = LDS ? sh_tab : ws.bound;
     int32_t *count = LDS ? reinterpret_cast<int32_t *>(sh_tab + n) : ws.count;
-    table_body<KIND>(P, seed, instance, ws_raw, status, lse_out, bound, count, eps, B_max, B_used,
-                     blockIdx.x, gridDim.x);
+    table_body<KIND, NT>(P, seed, instance, ws_raw, status, lse_out, bound, count, eps, B_max,
+                         B_used, blockIdx.x, gridDim.x);
 }
 
 // Stratified/systematic tables with LDS boundaries split the counts over up
@@ -85,32 +83,49 @@ __global__ __launch_bounds__(kTileThreads) void table_kernel(int64_t P, uint64_t
 // boundaries and the counts are exact.
 constexpr int64_t kTableParts = 64;
 
-template <int KIND>
-int launch_table(int64_t P, uint64_t seed, uint32_t instance, char *w, int32_t *status,
-                  double *lse_out, hipStream_t stream, double eps = 0.0, uint32_t B_max = 0,
-                  uint32_t *B_used = nullptr)
+// Beyond 1024 tiles the table blocks run kTableWideThreads threads: the
+// element-wise passes and the counts spread over four waves per SIMD, while
+// the runs and their scans stay with the first kTileThreads threads, so the
+// boundaries are the same sums.
+constexpr int kTableWideThreads = 512;
+
+template <int KIND, int NT>
+int launch_table_nt(int64_t P, uint64_t seed, uint32_t instance, char *w, int32_t *status,
+                    double *lse_out, hipStream_t stream, double eps, uint32_t B_max,
+                    uint32_t *B_used)
 {
     const int64_t n = num_tiles(P);
     if (n <= kTableLdsTiles) {
         int64_t parts = 1;
         if (KIND == kStratified || KIND == kSystematic) {
-            parts = (n + kTileThreads - 1) / kTileThreads;
+            parts = (n + NT - 1) / NT;
             parts = parts > kTableParts ? kTableParts : parts;
         }
         // a block's counts (one extra); only stratified and systematic count
         const bool counts = KIND == kStratified || KIND == kSystematic;
         const int64_t slice = counts ? (n + parts - 1) / parts + 2 : 0;
         const size_t smem = (size_t)n * sizeof(double) + (size_t)slice * sizeof(int32_t);
-        if (allow_dynamic_lds(reinterpret_cast<const void *>(&table_kernel<KIND, true>), smem))
+        if (allow_dynamic_lds(reinterpret_cast<const void *>(&table_kernel<KIND, true, NT>), smem))
             return -3;
-        hipLaunchKernelGGL((table_kernel<KIND, true>), dim3((uint32_t)parts), dim3(kTileThreads),
-                           smem, stream, P, seed, instance, w, status, lse_out, eps, B_max,
-                           B_used);
+        hipLaunchKernelGGL((table_kernel<KIND, true, NT>), dim3((uint32_t)parts), dim3(NT), smem,
+                           stream, P, seed, instance, w, status, lse_out, eps, B_max, B_used);
     } else {
-        hipLaunchKernelGGL((table_kernel<KIND, false>), dim3(1), dim3(kTileThreads), 0, stream, P,
-                           seed, instance, w, status, lse_out, eps, B_max, B_used);
+        hipLaunchKernelGGL((table_kernel<KIND, false, NT>), dim3(1), dim3(NT), 0, stream, P, seed,
+                           instance, w, status, lse_out, eps, B_max, B_used);
     }
     return 0;
+}
+
+template <int KIND>
+int launch_table(int64_t P, uint64_t seed, uint32_t instance, char *w, int32_t *status,
+                  double *lse_out, hipStream_t stream, double eps = 0.0, uint32_t B_max = 0,
+                  uint32_t *B_used = nullptr)
+{
+    if (num_tiles(P) > (int64_t)kTileThreads * kRegTiles)
+        return launch_table_nt<KIND, kTableWideThreads>(P, seed, instance, w, status, lse_out,
+                                                        stream, eps, B_max, B_used);
+    return launch_table_nt<KIND, kTileThreads>(P, seed, instance, w, status, lse_out, stream, eps,
+                                               B_max, B_used);
 }
 
 template <int KIND, bool FUSED>

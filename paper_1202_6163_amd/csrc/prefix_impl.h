@@ -266,19 +266,28 @@ struct TableSums {
 constexpr int kRegTiles = 4;
 constexpr int kRunBatch = 8;  // a thread's run is read this many entries at a time
 
-// Tiles each thread loads per 16-byte vector group in the long-run passes,
-// and groups in flight at once.
-constexpr int kLoadGroups = 4;
+// 16-byte vector groups (four tiles each) a thread has in flight at once in
+// the long-run passes: fewer with wide blocks, whose threads have fewer
+// registers and fewer groups each.
+template <int NT>
+constexpr int load_groups()
+{
+    return NT >= 1024 ? 2 : 4;
+}
 
 // The boundaries once each thread holds its run's tile values: in
 // registers (reg: mt, S for tiles t0 .. t1-1, at most kRegTiles) or, for
 // longer runs, the sums in bound[] and the maxima in ws.tile_max; fl and m
 // are the thread's OR of flags and max over its run. LONG: callers that may
 // pass more than 1024 tiles (the table launches), where the element-wise
-// passes load 16-byte vectors, kLoadGroups groups at a time; the other
+// passes load 16-byte vectors, load_groups() groups at a time; the other
 // callers keep the compact strided loops (same operations on every value,
-// so the same bits, with fewer registers).
-template <bool LONG>
+// so the same bits, with fewer registers). NT: the block's threads (a
+// multiple of kTileThreads). The runs and their scans always belong to the
+// first kTileThreads threads (tile_run), so the association of every sum is
+// the same for any NT; the other threads only share the element-wise passes
+// and see empty runs.
+template <bool LONG, int NT = kTileThreads>
 __device__ __forceinline__ TableSums boundaries_tail(const WsView &ws, int64_t n, int64_t t0, int64_t t1,
                                             bool reg, int fl, float m, float mt[kRegTiles],
                                             double S[kRegTiles], double *bound);
@@ -297,9 +306,10 @@ __device__ __forceinline__ void tile_run(int64_t n, int64_t *t0, int64_t *t1, bo
     *t1 = min(n, *t0 + per);
 }
 
-template <bool LONG>
+template <bool LONG, int NT = kTileThreads>
 __device__ inline TableSums boundaries(const WsView &ws, int64_t P, double *bound)
 {
+    static_assert(NT % kTileThreads == 0, "whole 256-thread groups");
     const int64_t n = num_tiles(P);
     const int tid = threadIdx.x;
     int64_t t0, t1;
@@ -339,7 +349,8 @@ __device__ inline TableSums boundaries(const WsView &ws, int64_t P, double *boun
         // groups issued before the first is used; the sections are 256-byte
         // aligned); only the sums below follow each thread's contiguous run.
         // The maximum and the OR do not depend on the order they are taken in.
-        constexpr int64_t span = 4 * kTileThreads;
+        constexpr int64_t span = 4 * NT;
+        constexpr int kLoadGroups = load_groups<NT>();
         const int64_t n4 = n & ~(int64_t)3;
         for (int64_t c = 4 * (int64_t)tid; c < n4; c += span * kLoadGroups) {
             float4 mv[kLoadGroups];
@@ -366,30 +377,31 @@ __device__ inline TableSums boundaries(const WsView &ws, int64_t P, double *boun
                 }
             }
         }
-        for (int64_t t = n4 + tid; t < n; t += kTileThreads) {
+        for (int64_t t = n4 + tid; t < n; t += NT) {
             fl |= ws.tile_flags[t];
             m = fmaxf(m, ws.tile_max[t]);
             bound[t] = ws.tile_sum[t];
         }
     } else {
 #pragma unroll 8
-        for (int64_t t = tid; t < n; t += kTileThreads) {
+        for (int64_t t = tid; t < n; t += NT) {
             fl |= ws.tile_flags[t];
             m = fmaxf(m, ws.tile_max[t]);
             bound[t] = ws.tile_sum[t];
         }
     }
-    return boundaries_tail<LONG>(ws, n, t0, t1, reg, fl, m, mt, S, bound);
+    return boundaries_tail<LONG, NT>(ws, n, t0, t1, reg, fl, m, mt, S, bound);
 }
 
-template <bool LONG>
+template <bool LONG, int NT>
 __device__ __forceinline__ TableSums boundaries_tail(const WsView &ws, int64_t n, int64_t t0, int64_t t1,
                                             bool reg, int fl, float m, float mt[kRegTiles],
                                             double S[kRegTiles], double *bound)
 {
-    __shared__ double redd[kNW];
-    __shared__ float redf[kNW];
-    __shared__ int redi[kNW];
+    constexpr int NW = NT / kWave;
+    __shared__ double redd[NW];
+    __shared__ float redf[NW];
+    __shared__ int redi[NW];
     __shared__ double sh_W;
     const int tid = threadIdx.x;
     // flags and max in one barrier (redi/redf are next written after later barriers)
@@ -403,7 +415,7 @@ __device__ __forceinline__ TableSums boundaries_tail(const WsView &ws, int64_t n
     fl = 0;
     m = -INFINITY;
 #pragma unroll
-    for (int w = 0; w < kNW; ++w) {
+    for (int w = 0; w < NW; ++w) {
         fl |= redi[w];
         m = fmaxf(m, redf[w]);
     }
@@ -425,7 +437,8 @@ __device__ __forceinline__ TableSums boundaries_tail(const WsView &ws, int64_t n
         if (LONG) {
             // the tiles this thread loaded above, their maxima read again
             // (now from L2) as 16-byte vectors, kLoadGroups groups at a time
-            constexpr int64_t span = 4 * kTileThreads;
+            constexpr int64_t span = 4 * NT;
+            constexpr int kLoadGroups = load_groups<NT>();
             const int64_t n4 = n & ~(int64_t)3;
             for (int64_t c = 4 * (int64_t)tid; c < n4; c += span * kLoadGroups) {
                 float4 mv[kLoadGroups];
@@ -445,19 +458,23 @@ __device__ __forceinline__ TableSums boundaries_tail(const WsView &ws, int64_t n
                     }
                 }
             }
-            for (int64_t t = n4 + tid; t < n; t += kTileThreads) rescale(t, ws.tile_max[t]);
+            for (int64_t t = n4 + tid; t < n; t += NT) rescale(t, ws.tile_max[t]);
         } else {
 #pragma unroll 8
-            for (int64_t t = tid; t < n; t += kTileThreads) rescale(t, ws.tile_max[t]);
+            for (int64_t t = tid; t < n; t += NT) rescale(t, ws.tile_max[t]);
         }
         __syncthreads();  // the runs below cross the element-wise ownership (reg is uniform)
+        // Each pass reads a batch of the run at once; entries of a batch past
+        // the run's end stand for its last entry (so every access stays in
+        // the thread's run and none waits on a branch) and change nothing.
         for (int64_t c = t0; c < t1; c += kRunBatch) {
+            const int lim = (int)min((int64_t)kRunBatch, t1 - c);
+            const double *src = bound + c;
             double v[kRunBatch];
 #pragma unroll
-            for (int k = 0; k < kRunBatch; ++k) v[k] = c + k < t1 ? bound[c + k] : 0.0;
+            for (int k = 0; k < kRunBatch; ++k) v[k] = src[k < lim ? k : lim - 1];
 #pragma unroll
-            for (int k = 0; k < kRunBatch; ++k)
-                if (c + k < t1) local += v[k];  // in tile order
+            for (int k = 0; k < kRunBatch; ++k) local = k < lim ? local + v[k] : local;  // in tile order
         }
     }
     double run = block_exclusive_sum(local, redd);
@@ -473,18 +490,18 @@ __device__ __forceinline__ TableSums boundaries_tail(const WsView &ws, int64_t n
         }
     } else {
         for (int64_t c = t0; c < t1; c += kRunBatch) {
+            const int lim = (int)min((int64_t)kRunBatch, t1 - c);
+            double *dst = bound + c;
             double v[kRunBatch];
 #pragma unroll
-            for (int k = 0; k < kRunBatch; ++k) v[k] = c + k < t1 ? bound[c + k] : 0.0;
+            for (int k = 0; k < kRunBatch; ++k) v[k] = dst[k < lim ? k : lim - 1];
 #pragma unroll
             for (int k = 0; k < kRunBatch; ++k) {
-                if (c + k < t1) {
-                    run += v[k];
-                    bound[c + k] = run;
-                    tmax = run;
-                }
+                run = k < lim ? run + v[k] : run;
+                dst[k < lim ? k : lim - 1] = run;  // past the run: the last entry's value again
             }
         }
+        if (t0 < t1) tmax = run;  // running sums grow within a thread
     }
     const double carry = block_exclusive_max(tmax, redd);
     if (reg) {
@@ -498,20 +515,21 @@ __device__ __forceinline__ TableSums boundaries_tail(const WsView &ws, int64_t n
             }
         }
     } else {
+        double last = 0.0;
         for (int64_t c = t0; c < t1; c += kRunBatch) {
+            const int lim = (int)min((int64_t)kRunBatch, t1 - c);
+            double *dst = bound + c;
             double v[kRunBatch];
 #pragma unroll
-            for (int k = 0; k < kRunBatch; ++k) v[k] = c + k < t1 ? bound[c + k] : 0.0;
+            for (int k = 0; k < kRunBatch; ++k) v[k] = dst[k < lim ? k : lim - 1];
 #pragma unroll
             for (int k = 0; k < kRunBatch; ++k) {
-                const int64_t t = c + k;
-                if (t < t1) {
-                    const double b = fmax(v[k], carry);
-                    bound[t] = b;
-                    if (t == n - 1) sh_W = b;
-                }
+                const double b = fmax(v[k], carry);
+                dst[k < lim ? k : lim - 1] = b;
+                last = k < lim ? b : last;
             }
         }
+        if (t0 < t1 && t1 == n) sh_W = last;
     }
     __syncthreads();
     return TableSums{0, m, sh_W};
@@ -530,9 +548,11 @@ __device__ __forceinline__ TableSums boundaries_tail(const WsView &ws, int64_t n
 // they meet. Only the tile holding a window's first draw can reach into it
 // (a later tile's remainder starts more than kWindow past its own first
 // draw), so that tile writes the window's entry: itself or -1. Every entry
-// is written exactly once.
-template <int KIND>
-__device__ void table_body(int64_t P, uint64_t seed, uint32_t instance, char *ws_raw,
+// is written exactly once. Inlined into every kernel, so that the LDS
+// boundaries are addressed as LDS: a called body would reach them through
+// flat (generic) loads and stores, and would carry the call's registers.
+template <int KIND, int NT = kTileThreads>
+__device__ __forceinline__ void table_body(int64_t P, uint64_t seed, uint32_t instance, char *ws_raw,
                            int32_t *status, double *lse_out, double *bound, int32_t *count,
                            double eps = 0.0, uint32_t B_max = 0, uint32_t *B_used = nullptr,
                            int part = 0, int parts = 1)
@@ -542,7 +562,7 @@ __device__ void table_body(int64_t P, uint64_t seed, uint32_t instance, char *ws
     const int64_t n = num_tiles(P);
     const int tid = threadIdx.x;
     const bool staged = bound != ws.bound;
-    const TableSums sums = boundaries<true>(ws, P, bound);
+    const TableSums sums = boundaries<true, NT>(ws, P, bound);
     if (sums.flags) {
         if (tid == 0 && part == 0) {
             h->flags = sums.flags;
@@ -559,19 +579,19 @@ __device__ void table_body(int64_t P, uint64_t seed, uint32_t instance, char *ws
     const int64_t u0 = n * part / parts, u1 = n * (part + 1) / parts;  // this block's tiles
     const double W = sums.W, delta = W / (double)P;
     if (staged)
-        for (int64_t t = u0 + tid; t < u1; t += kTileThreads) ws.bound[t] = bound[t];
+        for (int64_t t = u0 + tid; t < u1; t += NT) ws.bound[t] = bound[t];
     if (KIND == kStratified || KIND == kSystematic) {
         const double u_sys = KIND == kSystematic ? systematic_offset(seed, instance) : 0.0;
         // counts of tiles [c0, u1), c0 = u0 - 1 (that one gives the first tile's lo);
         // count[t - c0] holds tile t's (the block's own slice of scratch)
         const int64_t c0 = u0 > 0 ? u0 - 1 : 0;
-        for (int64_t t = c0 + tid; t < u1; t += kTileThreads) {
+        for (int64_t t = c0 + tid; t < u1; t += NT) {
             const int32_t c = (int32_t)count_below<KIND>(bound[t], P, W, delta, seed, instance, u_sys);
             count[t - c0] = c;
             if (count != ws.count && t >= u0) ws.count[t] = c;
         }
         __syncthreads();
-        for (int64_t t = u0 + tid; t < u1; t += kTileThreads) {
+        for (int64_t t = u0 + tid; t < u1; t += NT) {
             const int64_t lo = t > 0 ? count[t - 1 - c0] : 0, hi = count[t - c0];
             const int64_t M = (lo & ~(int64_t)3) + kChunk;
             for (int64_t q = (lo + kWindow - 1) / kWindow; q * kWindow < hi; ++q)
