@@ -11,7 +11,10 @@ shaped like the target workload. Results are stored in tuning.json next to
 this file, keyed by device name and library version, and applied when the
 binding is imported.
 
-    python -m paper_1202_6163_amd.autotune [--quick]
+    python -m paper_1202_6163_amd.autotune [--quick] [--batch-only]
+
+--batch-only keeps the stored single-call tuning and tunes the batched
+launches alone.
 """
 import argparse
 import itertools
@@ -84,6 +87,20 @@ def tune_batch(torch, rs, instances, candidates, reps=5):
     return results
 
 
+def tune_batch_candidates(torch, rs, quick):
+    """The batched launches' candidates on the target-shaped batch: (best,
+    every result sorted by time)."""
+    insts = batch_instances(torch)
+    bcands = [dict(chains_per_item=c, unroll=u, lds_max_p=l, blocks=bl)
+              for c, u, l, bl in itertools.product([512, 1024, 2048], [4, 8, 16],
+                                                   [0, 8192, 32768], [0, 1024])]
+    if quick:
+        bcands = bcands[::3]
+    bres = tune_batch(torch, rs, insts, bcands)
+    print("batch best", bres[0][1], f"{bres[0][0]:.3f} ms", file=sys.stderr, flush=True)
+    return bres[0][1], bres
+
+
 def batch_instances(torch, n=1024, seed=0):
     from . import workloads
     P, sig = workloads.batch_instances(n, seed=seed)
@@ -103,10 +120,38 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--quick", action="store_true")
     ap.add_argument("--out", default=TUNING_FILE)
+    ap.add_argument("--batch-only", action="store_true")
     args = ap.parse_args()
     import torch
     import paper_1202_6163_amd.api as rs
     from ._lib import lib
+
+    key = device_key(torch, lib)
+    try:
+        rec = json.load(open(args.out))
+    except (OSError, ValueError):
+        rec = {}
+    if args.batch_only and "metropolis" not in rec.get(key, {}):
+        # the stored tuning next to the package, when --out names a new file
+        try:
+            stored = json.load(open(TUNING_FILE)).get(key, {})
+        except (OSError, ValueError):
+            stored = {}
+        if "metropolis" not in stored:
+            raise SystemExit(f"--batch-only: no stored single-call tuning for {key}")
+        rec[key] = stored
+
+    if args.batch_only:
+        entry = dict(rec[key])
+        rs.rs_metropolis_set_tuning(**entry["metropolis"])
+        best_b, bres = tune_batch_candidates(torch, rs, args.quick)
+        entry["batch"] = best_b
+        entry["batch_top"] = [dict(ms=float(t), **c) for t, c in bres[:5]]
+        rec[key] = entry
+        with open(args.out, "w") as f:
+            json.dump(rec, f, indent=1)
+        print(json.dumps(rec[key]), flush=True)
+        return
 
     points = [(1 << 12, 32), (1 << 14, 64), (1 << 16, 64), (1 << 18, 32), (1 << 20, 32),
               (1 << 20, 256)]
@@ -121,21 +166,7 @@ def main():
     print("metropolis best", best_m, f"{mres[0][0]:.3f} ms", file=sys.stderr, flush=True)
     rs.rs_metropolis_set_tuning(**best_m)
 
-    insts = batch_instances(torch)
-    bcands = [dict(chains_per_item=c, unroll=u, lds_max_p=l, blocks=bl)
-              for c, u, l, bl in itertools.product([512, 1024, 2048], [8, 16],
-                                                   [0, 8192, 32768], [0, 1024])]
-    if args.quick:
-        bcands = bcands[::3]
-    bres = tune_batch(torch, rs, insts, bcands)
-    best_b = bres[0][1]
-    print("batch best", best_b, f"{bres[0][0]:.3f} ms", file=sys.stderr, flush=True)
-
-    key = device_key(torch, lib)
-    try:
-        rec = json.load(open(args.out))
-    except (OSError, ValueError):
-        rec = {}
+    best_b, bres = tune_batch_candidates(torch, rs, args.quick)
     # the staging threshold's effect: the best candidate with each threshold,
     # per point (P <= 16384 can be staged; 40960 also stages 2^15-2^16 points
     # if they fit, which they do not at the points used here)
