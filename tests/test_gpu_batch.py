@@ -167,6 +167,34 @@ def test_batch_full_workload_and_graph_replays(rs):
             assert torch.equal(d["anc"], ref[k]), (rep, k)
 
 
+def test_batch_long_tables_equal_single_calls(rs):
+    # instances beyond 1024 tiles: the single calls' table launch runs
+    # 512-thread blocks there, the batch's table launch 256-thread blocks
+    # (and beyond 4096 tiles keeps its boundaries in the workspace), with the
+    # runs and scans on the first 256 threads either way: the same bits
+    from paper_1202_6163_amd.batch import Batch
+    specs = [("stratified", (1 << 20) + 5, 4), ("systematic", 5_000_000, 0),
+             ("metropolis_adaptive", 3_000_001, 0), ("stratified", 1000, 4),
+             ("systematic", (1 << 22) + 3, 4)]
+    insts = []
+    for k, (kind, Pk, D) in enumerate(specs):
+        print(f"batch long tables: instance {k} {kind} P={Pk}", flush=True)
+        lw = torch.from_numpy(workloads.normal_logweights(Pk, 1.0, 300 + k)).cuda()
+        d = dict(lw=lw, anc=torch.full((Pk,), -7, dtype=torch.int32, device="cuda"), kind=kind,
+                 B=64, seed=77 + k, instance=k, eps=0.01,
+                 status=torch.zeros(1, dtype=torch.int32, device="cuda"))
+        if kind != "metropolis_adaptive":
+            d["off"] = torch.full((Pk,), -7, dtype=torch.int32, device="cuda")
+        if D:
+            d["x_in"] = torch.from_numpy(workloads.state_rows_exact(Pk, D)).cuda()
+            d["x_out"] = torch.zeros_like(d["x_in"])
+        insts.append(d)
+    b = Batch(insts)
+    b.run()
+    torch.cuda.synchronize()
+    check_batch(rs, insts)
+
+
 def test_batch_instance_offset_equals_single_calls(rs):
     from paper_1202_6163_amd.batch import Batch
     insts = make_instances(16, 6, 13, 4, seed=4)

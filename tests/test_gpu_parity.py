@@ -242,13 +242,14 @@ def test_prefix_full_size(rs, kind, sigma):
 
 
 @pytest.mark.parametrize("kind", SORTED)
-def test_prefix_table_in_global_memory(rs, kind):
-    # more than 4096 tiles: the table launch keeps boundaries and counts in
-    # the workspace instead of LDS
-    P = 5_000_000
+@pytest.mark.parametrize("P", [5_000_000, (1 << 24) + 4099])
+def test_prefix_long_tables(rs, kind, P):
+    # beyond 1024 tiles the table launch runs 512-thread blocks over runs of
+    # many tiles per thread; beyond 16384 tiles (2^24 + 4099) it keeps the
+    # boundaries and counts in the workspace instead of LDS, in one block
     seed, inst = 6, 2
     lw = workloads.normal_logweights(P, 1.0, seed)
-    say(kind, "P=5e6 (table in global memory)")
+    say(kind, f"P={P} (long-run table)")
     anc_o, _, C_o = ORACLE_FN[kind](lw, seed, inst, want_cumw=True)
     C = torch.empty(P, dtype=torch.float64, device="cuda")
     off = torch.full((P,), -1, dtype=torch.int32, device="cuda")
