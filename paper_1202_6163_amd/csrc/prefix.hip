@@ -84,9 +84,10 @@ __global__ __launch_bounds__(NT) void table_kernel(int64_t P, uint64_t seed, uin
 constexpr int64_t kTableParts = 64;
 
 // Beyond 1024 tiles the table blocks run kTableWideThreads threads: the
-// element-wise passes and the counts spread over four waves per SIMD, while
+// element-wise passes and the counts spread over two waves per SIMD, while
 // the runs and their scans stay with the first kTileThreads threads, so the
-// boundaries are the same sums.
+// boundaries are the same sums. (At 1024 threads the 128-register cap puts
+// the passes' arrays in scratch memory.)
 constexpr int kTableWideThreads = 512;
 
 template <int KIND, int NT>
