@@ -78,8 +78,8 @@ __global__ __launch_bounds__(NT) void table_kernel(int64_t P, uint64_t seed, uin
 }
 
 // Stratified/systematic tables with LDS boundaries split the counts over up
-// to kTableParts blocks (one tile per thread up to 2^24 particles); the rest
-// run one block. The split changes no result: each block rebuilds the same
+// to kTableParts blocks (one count per thread up to 2^24 particles); the
+// rest run one block. The split changes no result: each block rebuilds the same
 // boundaries and the counts are exact.
 constexpr int64_t kTableParts = 64;
 
@@ -99,7 +99,9 @@ int launch_table_nt(int64_t P, uint64_t seed, uint32_t instance, char *w, int32_
     if (n <= kTableLdsTiles) {
         int64_t parts = 1;
         if (KIND == kStratified || KIND == kSystematic) {
-            parts = (n + NT - 1) / NT;
+            // at most NT - 1 tiles a block: with the one before its first
+            // tile, every thread then has at most one count
+            parts = (n + NT - 2) / (NT - 1);
             parts = parts > kTableParts ? kTableParts : parts;
         }
         // a block's counts (one extra); only stratified and systematic count
