@@ -578,6 +578,25 @@ __device__ __forceinline__ void table_body(int64_t P, uint64_t seed, uint32_t in
     }
     const int64_t u0 = n * part / parts, u1 = n * (part + 1) / parts;  // this block's tiles
     const double W = sums.W, delta = W / (double)P;
+    // The header, by the block's last thread: block 0 gives it at most
+    // NT - 1 counts, so its log (and eq. (5)'s count) overlap the others'
+    // counts instead of following them.
+    if (tid == NT - 1 && part == 0) {
+        const double lse = (double)sums.m + log(W);
+        h->m = sums.m;
+        h->W = W;
+        h->delta = delta;
+        h->lse = lse;
+        h->flags = 0;
+        if (lse_out) *lse_out = lse;
+        if (KIND == kAdaptiveB) {
+            // with m the largest log-weight the largest normalised weight is 1 / W
+            const uint32_t Bn = iterations_for(P, 1.0 / W, eps);
+            const uint32_t B = Bn < B_max ? Bn : B_max;
+            h->B = B;
+            if (B_used) *B_used = B;
+        }
+    }
     if (staged)
         for (int64_t t = u0 + tid; t < u1; t += NT) ws.bound[t] = bound[t];
     if (KIND == kStratified || KIND == kSystematic) {
@@ -596,20 +615,6 @@ __device__ __forceinline__ void table_body(int64_t P, uint64_t seed, uint32_t in
             const int64_t M = (lo & ~(int64_t)3) + kChunk;
             for (int64_t q = (lo + kWindow - 1) / kWindow; q * kWindow < hi; ++q)
                 ws.win[q] = (M < hi && M < (q + 1) * kWindow) ? (int32_t)t : -1;
-        }
-    }
-    if (tid == 0 && part == 0) {
-        h->m = sums.m;
-        h->W = W;
-        h->delta = delta;
-        h->lse = (double)sums.m + log(W);
-        h->flags = 0;
-        if (lse_out) *lse_out = h->lse;
-        if (KIND == kAdaptiveB) {
-            // with m the largest log-weight the largest normalised weight is 1 / W
-            const uint32_t Bn = iterations_for(P, 1.0 / W, eps);
-            h->B = Bn < B_max ? Bn : B_max;
-            if (B_used) *B_used = h->B;
         }
     }
 }
