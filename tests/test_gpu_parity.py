@@ -684,17 +684,19 @@ def test_resample_and_copy_row_widths(rs, kind, D, P, aligned):
 
 
 @pytest.mark.parametrize("kind", ["metropolis"] + PREFIX)
-def test_resample_and_copy_full_size_against_oracle(rs, kind):
+@pytest.mark.parametrize("P", [1 << 20, (1 << 22) + 3])
+def test_resample_and_copy_full_size_against_oracle(rs, kind, P):
     # the benchmark step's form and size: P = 2^20, D = 4, one shared
-    # multinomial-sized workspace, offspring for stratified/systematic
-    P, D, seed, inst, B = 1 << 20, 4, 21, 2, 32
+    # multinomial-sized workspace, offspring for stratified/systematic; and
+    # beyond 1024 tiles (the long-run table, multi-line multinomial groups)
+    D, seed, inst, B = 4, 21, 2, 32
     lw_h = workloads.normal_logweights(P, 1.0, seed)
     x_h = workloads.state_rows_exact(P, D)
     lw, x = dev(lw_h), dev(x_h)
     ws = rs.workspace(P, rs.MULTINOMIAL, lw.device)
     off = torch.full((P,), -1, dtype=torch.int32, device="cuda") if kind in SORTED else None
     st = torch.zeros(1, dtype=torch.int32, device="cuda")
-    say(kind, "resample_and_copy at P=2^20")
+    say(kind, f"resample_and_copy at P={P}")
     anc, xo = rs.resample_and_copy(kind, lw, x, seed, inst, B=B, off=off, ws=ws, status=st)
     anc_g, xo_g = host(anc), host(xo)
     assert int(host(st)[0]) == 0
