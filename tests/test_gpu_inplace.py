@@ -6,7 +6,7 @@ extra copies in particle order); hence also the multiset of rows of the
 ancestor-indexed copy. Offspring come from every resampler (oracle and
 library), from concentrated and adversarial patterns (holes dense where the
 extras are sparse, so a block's holes draw on many source tiles), up to
-P = 2^20 with ragged tails and row widths 1, 3, 4 and 16; invalid counts
+P = 5 000 000 with ragged tails and row widths 1, 3, 4 and 16; invalid counts
 leave the state unchanged and raise the flag; graph replays repeat the
 eager result.
 """
@@ -85,6 +85,17 @@ def test_library_metropolis_at_2_20(rs, D):
     x = workloads.state_rows_exact(P, D)
     check(rs, off_h, x, f"library Metropolis B={int(B.item())} D={D}")
     say(f"holes: {np.count_nonzero(off_h == 0) / P:.3f} of the slots")
+
+
+@pytest.mark.parametrize("P", [(1 << 22) + 5, 5_000_000])
+def test_beyond_4096_tiles(rs, P):
+    # more tiles than one block's prefix holds in a single pass: multinomial
+    # offspring from the oracle, rows of width 4
+    say(f"inplace: multinomial P={P}")
+    lw = workloads.normal_logweights(P, 2.0, 33)
+    anc, _ = oracle.multinomial(lw, 6, 0)
+    off, _ = oracle.ancestors_to_offspring(anc)
+    check(rs, off, workloads.state_rows_exact(P, 4), f"multinomial P={P}")
 
 
 @pytest.mark.parametrize("pattern", ["identity", "one_holds_all_first", "one_holds_all_last",
