@@ -565,7 +565,8 @@ def test_measurement_probes_run(rs):
 
 # ----------------------------------------------------------------- sorted-weight variants
 @pytest.mark.parametrize("kind", PREFIX)
-@pytest.mark.parametrize("P", [1, 5, 1000, 4096, 4097, 5000, 100003, 1 << 16, (1 << 20) + 3])
+@pytest.mark.parametrize("P", [1, 5, 1000, 4096, 4097, 5000, 100003, 1 << 16, (1 << 20) + 3,
+                               (1 << 22) + 1])
 def test_sorted_variant_parity(rs, kind, P):
     seed, inst = P % 13 + 2, 1
     lw = workloads.normal_logweights(P, 1.5, seed)
